@@ -1,0 +1,198 @@
+/*
+ * qvm.h -- C ABI of the MI355X (gfx950) full-amplitude state-vector library.
+ *
+ * The method: a quantum program is a sequence of gates, each a 2^k x 2^k
+ * unitary on k target qubits with optional control qubits, applied as a
+ * linear map to the 2^n complex amplitudes of the state (paper, "Multi-
+ * simulation methods", noise-free Schroedinger simulation, full-amplitude
+ * backend).  The calls follow the paper's user-facing operations: allocate
+ * n qubits (init_qvm / qAlloc_many), apply gates with targets and controls
+ * (the gate set and .control() of "Structure of QPanda" and "A variety of
+ * convenient tools"), fuse gates into unitary blocks (Fusion /
+ * aggregate_operations, "Quantum circuit fusion"), and read out
+ * probabilities (prob_run_*), expectation values and measurement samples
+ * ("A variety of convenient tools").
+ *
+ * Conventions (the paper fixes none of them):
+ *   - qubit q is bit q of the amplitude index (qubit 0 least significant);
+ *   - amplitudes are interleaved (re, im): QVM_C64 = 2 x float (8 bytes),
+ *     QVM_C128 = 2 x double (16 bytes);
+ *   - a k-qubit matrix is row-major 2^k x 2^k complex given as (re, im)
+ *     double pairs, and bit r of its row/column index refers to targets[r];
+ *   - controls are 1-controls, given as a bit mask over qubits;
+ *   - bit strings returned by sampling are amplitude indices in the logical
+ *     qubit order above.
+ *
+ * Ownership: device buffers (amplitudes, workspace) belong to the caller,
+ * who keeps them alive until qvm_sv_destroy.  Host arrays passed in are
+ * read during the call only.  The library owns only its opaque handles.
+ *
+ * Streams: every call enqueues on the stream given at creation (a
+ * hipStream_t passed as void*; NULL = the null stream).  Calls that return
+ * host values synchronise that stream; all others are asynchronous.
+ *
+ * Errors: every call returns a qvm_status.  Arguments are validated before
+ * anything is enqueued (QVM_EARG / QVM_ERANGE).  A HIP error returns
+ * QVM_EDEVICE and marks the handle failed; later calls on it return
+ * QVM_ESTATE.  qvm_last_error() gives the calling thread's last message.
+ * No C++ exception crosses this interface.
+ */
+#ifndef QVM_H
+#define QVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QVM_OK = 0,
+    QVM_EARG = -1,          /* malformed argument (NULL, duplicate qubit, k out of range) */
+    QVM_ERANGE = -2,        /* qubit >= n, basis index >= 2^n, index out of range */
+    QVM_ENOMEM = -3,        /* workspace too small, host allocation failed */
+    QVM_EDEVICE = -4,       /* HIP runtime or launch error */
+    QVM_ESTATE = -5,        /* handle failed earlier, or is in the wrong state */
+    QVM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+} qvm_status;
+
+typedef enum { QVM_C64 = 1, QVM_C128 = 2 } qvm_dtype;
+
+#define QVM_MAX_QUBITS 34
+#define QVM_MAX_K 6
+
+/* Named gates (paper's gate set).  One-target kinds take targets[0]; RZZ and
+ * SWAP take two targets; QVM_G_MATRIX takes k targets and the matrix u.
+ * Angles in params: RX/RY/RZ/P/RZZ use params[0]; U3 uses (theta, phi,
+ * lambda) in the OpenQASM 2 form.  CNOT = X with one control, CZ = Z with one
+ * control, CR = P with one control, Toffoli = X with two controls. */
+typedef enum {
+    QVM_G_MATRIX = 0,
+    QVM_G_I = 1, QVM_G_H = 2, QVM_G_X = 3, QVM_G_Y = 4, QVM_G_Z = 5,
+    QVM_G_S = 6, QVM_G_SDG = 7, QVM_G_T = 8, QVM_G_TDG = 9,
+    QVM_G_RX = 10, QVM_G_RY = 11, QVM_G_RZ = 12, QVM_G_P = 13, QVM_G_U3 = 14,
+    QVM_G_RZZ = 15, QVM_G_SWAP = 16
+} qvm_gate_kind;
+
+/* One gate.  72 bytes, no padding surprises: int32 x 8, uint64, double x 3,
+ * pointer.  `u` is read only for QVM_G_MATRIX (2^k x 2^k, (re, im) doubles,
+ * row-major) and must be NULL otherwise. */
+typedef struct qvm_gate {
+    int32_t kind;
+    int32_t k;
+    int32_t targets[QVM_MAX_K];
+    uint64_t ctrl_mask;
+    double params[3];
+    const double* u;
+} qvm_gate;
+
+typedef struct qvm_sv qvm_sv;       /* a state vector bound to caller memory */
+
+/* ---------------------------------------------------------------- lowering */
+
+/* Gate lowering: writes the gate's 2^k x 2^k target matrix (controls not
+ * included) as (re, im) doubles into u_out (room for 2^(2k) complex).
+ * Angles are evaluated on the host in double precision.  Host-only; needs no
+ * GPU.  QVM_EARG for an unknown kind or a k that does not match the kind. */
+qvm_status qvm_gate_matrix(const qvm_gate* g, double* u_out);
+
+/* ------------------------------------------------------------ state vector */
+
+/* Bytes of device workspace a state of n qubits needs (reduction partials,
+ * sampling tables, plan data).  Host-only. */
+size_t qvm_workspace_bytes(int n_qubits, qvm_dtype dt);
+
+/* Bind a state of n qubits (1..QVM_MAX_QUBITS) to caller memory: amps_dev
+ * holds 2^n amplitudes of dtype dt (256-byte aligned), work_dev at least
+ * qvm_workspace_bytes(n, dt) bytes.  hip_stream may be NULL.  The amplitudes
+ * are not initialised; call qvm_init_basis.  The logical-to-physical qubit
+ * layout starts as the identity. */
+qvm_status qvm_sv_create(int n_qubits, qvm_dtype dt, void* amps_dev,
+                         void* work_dev, size_t work_bytes, void* hip_stream,
+                         qvm_sv** out);
+
+/* Release the handle.  Never frees caller buffers.  Accepts NULL. */
+qvm_status qvm_sv_destroy(qvm_sv* sv);
+
+/* Replace the stream later calls enqueue on. */
+qvm_status qvm_sv_set_stream(qvm_sv* sv, void* hip_stream);
+
+/* Set the state to the basis state |index> (0 = |0..0>) and reset the qubit
+ * layout to the identity.  QVM_ERANGE if index >= 2^n.  Asynchronous. */
+qvm_status qvm_init_basis(qvm_sv* sv, uint64_t index);
+
+/* Apply one gate (plain per-gate path: one pass over the state).  k <= 3 for
+ * dense matrices; any number of controls.  Asynchronous. */
+qvm_status qvm_apply(qvm_sv* sv, const qvm_gate* g);
+
+/* Apply a gate list in order with the plain per-gate path, in one call (the
+ * per-gate call overhead the paper measures at small n is paid once).
+ * The list is validated in full before anything is enqueued. */
+qvm_status qvm_run(qvm_sv* sv, const qvm_gate* gates, size_t n_gates);
+
+/* Current logical-to-physical qubit layout: perm_out[q] = physical bit of
+ * logical qubit q (n entries).  Host-only. */
+qvm_status qvm_get_layout(const qvm_sv* sv, int32_t* perm_out);
+
+/* Physically permute the amplitudes back to the identity layout (one pass
+ * per displaced qubit pair).  Asynchronous. */
+qvm_status qvm_reset_layout(qvm_sv* sv);
+
+/* -------------------------------------------------------------- readout */
+
+/* Probabilities |psi_i|^2 in double precision (single-precision states are
+ * widened before squaring).  m = n and qubits = NULL gives all 2^n values
+ * in logical index order; otherwise the marginal over qubits[0..m-1], with
+ * bit r of the output index <-> qubits[r].  out_host holds 2^m doubles.
+ * m <= 24 for marginals.  Synchronous. */
+qvm_status qvm_probabilities(qvm_sv* sv, int m, const int32_t* qubits,
+                             double* out_host);
+
+/* <Z_q> for every logical qubit in one pass over the state, double-precision
+ * accumulation.  out_host holds n doubles.  Synchronous. */
+qvm_status qvm_expect_z_all(qvm_sv* sv, double* out_host);
+
+/* Pauli-string expectations <psi|P_t|psi> for strings in symplectic form
+ * (x_mask: qubits carrying X or Y; z_mask: qubits carrying Z or Y; over
+ * logical qubits).  Terms sharing an x_mask share one pass.  out_terms_host
+ * (n_terms doubles, nullable) receives each term without its coefficient;
+ * out_sum_host (nullable) receives sum_t coeff[t] <P_t>; coeff may be NULL
+ * when out_sum_host is NULL.  Double-precision accumulation.  Synchronous. */
+qvm_status qvm_expect_pauli(qvm_sv* sv, size_t n_terms, const uint64_t* x_mask,
+                            const uint64_t* z_mask, const double* coeff,
+                            double* out_terms_host, double* out_sum_host);
+
+/* Draw samples: for each uniform u in [0,1), the smallest logical index i
+ * with C_i > u * C_{N-1}, where C is the cumulative probability in logical
+ * index order accumulated in double precision (the total absorbs norm
+ * drift).  Synchronous. */
+qvm_status qvm_sample(qvm_sv* sv, size_t n_samples, const double* uniforms_host,
+                      uint64_t* out_host);
+
+/* Squared norm sum_i |psi_i|^2 in double precision.  Synchronous. */
+qvm_status qvm_norm(qvm_sv* sv, double* out);
+
+/* Scale the state to unit norm (norm computed in double precision).
+ * norm_before (nullable) receives the squared norm before scaling.
+ * QVM_ESTATE if the norm is zero or not finite.  Synchronous. */
+qvm_status qvm_renormalize(qvm_sv* sv, double* norm_before);
+
+/* Copy amplitudes [first, first+count) in logical index order to the host as
+ * (re, im) doubles.  Synchronous. */
+qvm_status qvm_copy_amplitudes(qvm_sv* sv, uint64_t first, uint64_t count,
+                               double* out_host);
+
+/* Copy the amplitudes at the given logical indices to the host as (re, im)
+ * doubles.  Synchronous. */
+qvm_status qvm_gather_amplitudes(qvm_sv* sv, size_t count,
+                                 const uint64_t* logical_idx, double* out_host);
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char* qvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QVM_H */

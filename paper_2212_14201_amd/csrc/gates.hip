@@ -1,0 +1,239 @@
+// Plain per-gate kernels: one pass over the amplitudes per gate.
+//
+// Every kernel enumerates exactly the amplitudes a gate changes: a work
+// index w is spread over the free bits of the amplitude index ("deposit"),
+// and the fixed bits (targets at 0, controls at 1, or a phase/move
+// condition) are OR-ed in.  Lanes take consecutive w, so accesses stay
+// coalesced whenever the lowest physical bits are free bits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace qvm {
+
+template <typename R> struct C2;
+template <> struct C2<float> { using T = float2; };
+template <> struct C2<double> { using T = double2; };
+
+// Spread the bits of w over the zero bits of `fixed` (ascending order).
+__device__ __forceinline__ uint64_t deposit(uint64_t w, uint64_t fixed) {
+    while (fixed) {
+        uint64_t low = fixed & (~fixed + 1);
+        uint64_t lo = w & (low - 1);
+        w = ((w - lo) << 1) | lo;
+        fixed ^= low;
+    }
+    return w;
+}
+
+template <typename R, int K> struct DenseArgs {
+    uint64_t items, fixed, cmask;
+    uint64_t off[1 << K];
+    R m[2 << (2 * K)];               // 2^K x 2^K complex, row-major (re, im)
+};
+
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_dense(typename C2<R>::T* __restrict__ psi,
+                                               DenseArgs<R, K> a) {
+    using T = typename C2<R>::T;
+    constexpr int D = 1 << K;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.items; w += stride) {
+        uint64_t b = deposit(w, a.fixed) | a.cmask;
+        T v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = psi[b + a.off[j]];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                R mr = a.m[2 * (i * D + j)], mi = a.m[2 * (i * D + j) + 1];
+                re += mr * v[j].x - mi * v[j].y;
+                im += mr * v[j].y + mi * v[j].x;
+            }
+            T o;
+            o.x = re;
+            o.y = im;
+            psi[b + a.off[i]] = o;
+        }
+    }
+}
+
+template <typename R> struct DiagArgs {
+    uint64_t items, cmask;
+    int k;
+    int t[3];
+    R d[16];                          // up to 2^3 complex entries
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag(typename C2<R>::T* __restrict__ psi, DiagArgs<R> a) {
+    using T = typename C2<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.items; w += stride) {
+        uint64_t i = deposit(w, a.cmask) | a.cmask;
+        int j = 0;
+        for (int r = 0; r < a.k; ++r) j |= (int)((i >> a.t[r]) & 1) << r;
+        T v = psi[i];
+        R dr = a.d[2 * j], di = a.d[2 * j + 1];
+        T o;
+        o.x = dr * v.x - di * v.y;
+        o.y = dr * v.y + di * v.x;
+        psi[i] = o;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_phase(typename C2<R>::T* __restrict__ psi, uint64_t items,
+                                               uint64_t cmask, uint64_t cval, R pr, R pi) {
+    using T = typename C2<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
+        uint64_t i = deposit(w, cmask) | cval;
+        T v = psi[i];
+        T o;
+        o.x = pr * v.x - pi * v.y;
+        o.y = pr * v.y + pi * v.x;
+        psi[i] = o;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_swappair(typename C2<R>::T* __restrict__ psi, uint64_t items,
+                                                  uint64_t fixed, uint64_t cval, uint64_t xmask) {
+    using T = typename C2<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
+        uint64_t i = deposit(w, fixed) | cval;
+        uint64_t j = i ^ xmask;
+        T a = psi[i], b = psi[j];
+        psi[i] = b;
+        psi[j] = a;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_basis(typename C2<R>::T* __restrict__ psi, uint64_t N,
+                                               uint64_t idx) {
+    using T = typename C2<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        T v;
+        v.x = i == idx ? (R)1 : (R)0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+static unsigned grid_for(uint64_t items) {
+    uint64_t g = (items + 255) / 256;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 20));
+}
+
+static inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+template <typename R, int K>
+static qvm_status launch_dense_k(qvm_sv* sv, const LOp& op) {
+    using T = typename C2<R>::T;
+    DenseArgs<R, K> a{};
+    uint64_t tmask = 0;
+    for (int r = 0; r < K; ++r) tmask |= 1ull << op.t[r];
+    a.fixed = tmask | op.cmask;
+    a.cmask = op.cmask;
+    a.items = 1ull << (sv->n - popc(a.fixed));
+    for (int j = 0; j < (1 << K); ++j) {
+        uint64_t o = 0;
+        for (int r = 0; r < K; ++r)
+            if ((j >> r) & 1) o |= 1ull << op.t[r];
+        a.off[j] = o;
+    }
+    for (int i = 0; i < (1 << (2 * K)); ++i) {
+        a.m[2 * i] = (R)op.m[i].real();
+        a.m[2 * i + 1] = (R)op.m[i].imag();
+    }
+    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
+                       (T*)sv->amps, a);
+    QVM_LAUNCH_CHECK(sv);
+    return QVM_OK;
+}
+
+template <typename R>
+static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
+    using T = typename C2<R>::T;
+    switch (op.cls) {
+        case OP_PHASE: {
+            if (op.phase == cd(1.0, 0.0)) return QVM_OK;   // identity
+            uint64_t items = 1ull << (sv->n - popc(op.cond_mask));
+            hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
+                               (T*)sv->amps, items, op.cond_mask, op.cond_val,
+                               (R)op.phase.real(), (R)op.phase.imag());
+            QVM_LAUNCH_CHECK(sv);
+            return QVM_OK;
+        }
+        case OP_DIAG: {
+            if (op.k > 3) return fail(QVM_EUNSUPPORTED, "diagonal gate with k > 3 on the plain path");
+            DiagArgs<R> a{};
+            a.cmask = op.cmask;
+            a.items = 1ull << (sv->n - popc(op.cmask));
+            a.k = op.k;
+            for (int r = 0; r < op.k; ++r) a.t[r] = op.t[r];
+            for (int j = 0; j < (1 << op.k); ++j) {
+                a.d[2 * j] = (R)op.m[j].real();
+                a.d[2 * j + 1] = (R)op.m[j].imag();
+            }
+            hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
+                               (T*)sv->amps, a);
+            QVM_LAUNCH_CHECK(sv);
+            return QVM_OK;
+        }
+        case OP_SWAPPAIR: {
+            uint64_t fixed = op.cond_mask | op.hbit;
+            uint64_t items = 1ull << (sv->n - popc(fixed));
+            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
+                               (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
+            QVM_LAUNCH_CHECK(sv);
+            return QVM_OK;
+        }
+        case OP_DENSE:
+            switch (op.k) {
+                case 1: return launch_dense_k<R, 1>(sv, op);
+                case 2: return launch_dense_k<R, 2>(sv, op);
+                case 3: return launch_dense_k<R, 3>(sv, op);
+                default: return fail(QVM_EUNSUPPORTED, "dense gate with k > 3 on the plain path");
+            }
+    }
+    return fail(QVM_EARG, "bad op class");
+}
+
+qvm_status launch_op(qvm_sv* sv, const LOp& op) {
+    return sv->dt == QVM_C64 ? launch_op_t<float>(sv, op) : launch_op_t<double>(sv, op);
+}
+
+qvm_status launch_init_basis(qvm_sv* sv, uint64_t idx) {
+    uint64_t N = 1ull << sv->n;
+    if (sv->dt == QVM_C64)
+        hipLaunchKernelGGL((k_basis<float>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
+                           (float2*)sv->amps, N, idx);
+    else
+        hipLaunchKernelGGL((k_basis<double>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
+                           (double2*)sv->amps, N, idx);
+    QVM_LAUNCH_CHECK(sv);
+    return QVM_OK;
+}
+
+qvm_status launch_swap_bits(qvm_sv* sv, int a, int b) {
+    if (a == b) return QVM_OK;
+    LOp op{};
+    op.cls = OP_SWAPPAIR;
+    op.xmask = (1ull << a) | (1ull << b);
+    // representative i: bit a = 0, bit b = 1; partner has them exchanged
+    op.hbit = 1ull << a;
+    op.cond_mask = 1ull << b;
+    op.cond_val = 1ull << b;
+    return launch_op(sv, op);
+}
+
+}  // namespace qvm

@@ -1,0 +1,296 @@
+"""Python binding of ``libqvm.so`` (argument marshalling only).
+
+Every operation runs in the HIP library; this module converts gate lists
+into ``qvm_gate`` records, hands torch-owned device buffers and the current
+torch stream to the C ABI, and turns status codes into exceptions.  There
+is no fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqvm.so")
+
+QVM_C64, QVM_C128 = 1, 2
+MAX_K = 6
+
+KIND = {"unitary": 0, "matrix": 0, "i": 1, "h": 2, "x": 3, "y": 4, "z": 5, "s": 6,
+        "sdg": 7, "t": 8, "tdg": 9, "rx": 10, "ry": 11, "rz": 12, "p": 13, "u3": 14,
+        "rzz": 15, "swap": 16}
+
+STATUS = {0: "QVM_OK", -1: "QVM_EARG", -2: "QVM_ERANGE", -3: "QVM_ENOMEM",
+          -4: "QVM_EDEVICE", -5: "QVM_ESTATE", -6: "QVM_EUNSUPPORTED"}
+
+
+class QvmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class QvmGate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("targets", ctypes.c_int32 * MAX_K), ("ctrl_mask", ctypes.c_uint64),
+                ("params", ctypes.c_double * 3), ("u", ctypes.POINTER(ctypes.c_double))]
+
+
+assert ctypes.sizeof(QvmGate) == 72
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_gp = ctypes.POINTER(QvmGate)
+
+_lib = None
+
+
+def _declare(L):
+    st = ctypes.c_int
+    sig = {
+        "qvm_gate_matrix": (st, [_gp, _dp]),
+        "qvm_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+        "qvm_sv_create": (st, [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp,
+                               ctypes.POINTER(_vp)]),
+        "qvm_sv_destroy": (st, [_vp]),
+        "qvm_sv_set_stream": (st, [_vp, _vp]),
+        "qvm_init_basis": (st, [_vp, ctypes.c_uint64]),
+        "qvm_apply": (st, [_vp, _gp]),
+        "qvm_run": (st, [_vp, _gp, ctypes.c_size_t]),
+        "qvm_get_layout": (st, [_vp, _i32p]),
+        "qvm_reset_layout": (st, [_vp]),
+        "qvm_probabilities": (st, [_vp, ctypes.c_int, _i32p, _dp]),
+        "qvm_expect_z_all": (st, [_vp, _dp]),
+        "qvm_expect_pauli": (st, [_vp, ctypes.c_size_t, _u64p, _u64p, _dp, _dp, _dp]),
+        "qvm_sample": (st, [_vp, ctypes.c_size_t, _dp, _u64p]),
+        "qvm_norm": (st, [_vp, _dp]),
+        "qvm_renormalize": (st, [_vp, _dp]),
+        "qvm_copy_amplitudes": (st, [_vp, ctypes.c_uint64, ctypes.c_uint64, _dp]),
+        "qvm_gather_amplitudes": (st, [_vp, ctypes.c_size_t, _u64p, _dp]),
+        "qvm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return sig
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_2212_14201_amd/build.py (no fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != 0:
+        msg = lib().qvm_last_error()
+        raise QvmError(status, msg.decode() if msg else "")
+    return status
+
+
+# ------------------------------------------------------------------ gates
+def _ctrl_mask(ctrls) -> int:
+    m = 0
+    for c in ctrls:
+        m |= 1 << int(c)
+    return m
+
+
+class GateArray:
+    """A packed array of qvm_gate records built from gate objects with
+    ``name``, ``targets``, ``controls``, ``params`` and (for explicit
+    unitaries) ``matrix`` attributes.  Keeps matrix buffers alive."""
+
+    def __init__(self, gates, params=None):
+        gates = list(gates)
+        self.n = len(gates)
+        self.arr = (QvmGate * max(1, self.n))()
+        self._keep = []
+        for i, g in enumerate(gates):
+            rec = self.arr[i]
+            kind = KIND[g.name]
+            rec.kind = kind
+            rec.k = len(g.targets)
+            for r, t in enumerate(g.targets):
+                rec.targets[r] = int(t)
+            rec.ctrl_mask = _ctrl_mask(g.controls)
+            ps = list(g.params)
+            pidx = getattr(g, "pidx", -1)
+            if params is not None and pidx is not None and pidx >= 0:
+                ps = [float(params[pidx])]
+            for j, p in enumerate(ps[:3]):
+                rec.params[j] = float(p)
+            if kind == 0:
+                m = np.ascontiguousarray(np.asarray(g.matrix, dtype=np.complex128))
+                buf = m.view(np.float64).ravel().copy()
+                self._keep.append(buf)
+                rec.u = buf.ctypes.data_as(_dp)
+            else:
+                rec.u = None
+
+    def ptr(self):
+        return ctypes.cast(self.arr, _gp)
+
+
+def gate_matrix(gate) -> np.ndarray:
+    """The library's lowering of one gate (host only)."""
+    ga = GateArray([gate])
+    k = len(gate.targets)
+    out = np.zeros(2 * (1 << (2 * k)), dtype=np.float64)
+    check(lib().qvm_gate_matrix(ga.ptr(), out.ctypes.data_as(_dp)))
+    return out.view(np.complex128).reshape(1 << k, 1 << k)
+
+
+def workspace_bytes(n: int, dtype: str) -> int:
+    return int(lib().qvm_workspace_bytes(n, _dt(dtype)))
+
+
+def _dt(dtype) -> int:
+    if dtype in ("c64", "complex64", QVM_C64):
+        return QVM_C64
+    if dtype in ("c128", "complex128", QVM_C128):
+        return QVM_C128
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def _stream_ptr(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class StateVector:
+    """2^n amplitudes in torch-owned device memory, driven by libqvm."""
+
+    def __init__(self, n: int, dtype: str = "c128", device="cuda", init: int | None = 0):
+        import torch
+        self.n = int(n)
+        self.dtype = "c64" if _dt(dtype) == QVM_C64 else "c128"
+        self.device = torch.device(device)
+        real = torch.float32 if self.dtype == "c64" else torch.float64
+        self.amps = torch.empty(2 << self.n, dtype=real, device=self.device)
+        self.work = torch.empty(workspace_bytes(self.n, self.dtype), dtype=torch.uint8,
+                                device=self.device)
+        h = _vp()
+        check(lib().qvm_sv_create(self.n, _dt(self.dtype), self.amps.data_ptr(),
+                                  self.work.data_ptr(), self.work.numel(),
+                                  _stream_ptr(self.device), ctypes.byref(h)))
+        self._h = h
+        if init is not None:
+            self.init_basis(init)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().qvm_sv_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sync_stream(self):
+        """Re-bind the handle to torch's current stream."""
+        check(lib().qvm_sv_set_stream(self._h, _stream_ptr(self.device)))
+
+    # --------------------------------------------------------- evolution
+    def init_basis(self, index: int = 0):
+        check(lib().qvm_init_basis(self._h, int(index)))
+
+    def apply(self, gate):
+        ga = GateArray([gate])
+        check(lib().qvm_apply(self._h, ga.ptr()))
+
+    def run(self, gates, params=None):
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates, params)
+        check(lib().qvm_run(self._h, ga.ptr(), ga.n))
+
+    def layout(self):
+        out = np.zeros(self.n, dtype=np.int32)
+        check(lib().qvm_get_layout(self._h, out.ctypes.data_as(_i32p)))
+        return out
+
+    def reset_layout(self):
+        check(lib().qvm_reset_layout(self._h))
+
+    # ------------------------------------------------------------ readout
+    def probabilities(self, qubits=None) -> np.ndarray:
+        if qubits is None:
+            out = np.empty(1 << self.n, dtype=np.float64)
+            check(lib().qvm_probabilities(self._h, self.n, None, out.ctypes.data_as(_dp)))
+            return out
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        out = np.empty(1 << q.size, dtype=np.float64)
+        check(lib().qvm_probabilities(self._h, q.size, q.ctypes.data_as(_i32p),
+                                      out.ctypes.data_as(_dp)))
+        return out
+
+    def expect_z_all(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float64)
+        check(lib().qvm_expect_z_all(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def expect_pauli(self, xs, zs, coeffs=None):
+        """Returns (per-term values, weighted sum or None)."""
+        xs = np.ascontiguousarray(xs, dtype=np.uint64)
+        zs = np.ascontiguousarray(zs, dtype=np.uint64)
+        terms = np.empty(xs.size, dtype=np.float64)
+        if coeffs is not None:
+            cs = np.ascontiguousarray(coeffs, dtype=np.float64)
+            tot = ctypes.c_double(0.0)
+            check(lib().qvm_expect_pauli(self._h, xs.size, xs.ctypes.data_as(_u64p),
+                                         zs.ctypes.data_as(_u64p), cs.ctypes.data_as(_dp),
+                                         terms.ctypes.data_as(_dp), ctypes.byref(tot)))
+            return terms, float(tot.value)
+        check(lib().qvm_expect_pauli(self._h, xs.size, xs.ctypes.data_as(_u64p),
+                                     zs.ctypes.data_as(_u64p), None,
+                                     terms.ctypes.data_as(_dp), None))
+        return terms, None
+
+    def sample(self, uniforms) -> np.ndarray:
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        out = np.empty(u.size, dtype=np.uint64)
+        check(lib().qvm_sample(self._h, u.size, u.ctypes.data_as(_dp),
+                               out.ctypes.data_as(_u64p)))
+        return out
+
+    def norm(self) -> float:
+        v = ctypes.c_double(0.0)
+        check(lib().qvm_norm(self._h, ctypes.byref(v)))
+        return float(v.value)
+
+    def renormalize(self) -> float:
+        v = ctypes.c_double(0.0)
+        check(lib().qvm_renormalize(self._h, ctypes.byref(v)))
+        return float(v.value)
+
+    def amplitudes(self, first: int = 0, count: int | None = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - first
+        out = np.empty(2 * count, dtype=np.float64)
+        check(lib().qvm_copy_amplitudes(self._h, int(first), int(count), out.ctypes.data_as(_dp)))
+        return out.view(np.complex128)
+
+    def gather(self, indices) -> np.ndarray:
+        idx = np.ascontiguousarray(indices, dtype=np.uint64)
+        out = np.empty(2 * idx.size, dtype=np.float64)
+        check(lib().qvm_gather_amplitudes(self._h, idx.size, idx.ctypes.data_as(_u64p),
+                                          out.ctypes.data_as(_dp)))
+        return out.view(np.complex128)

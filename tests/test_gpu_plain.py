@@ -1,0 +1,178 @@
+"""GPU parity of the plain per-gate path and the readouts against the oracle.
+
+Every test runs the HIP library through its C ABI on seeded inputs from
+``workloads`` and compares element by element with the FP64 oracle:
+max-abs amplitude error <= 1e-12 for complex128, the stated per-result bound
+for complex64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.util import C128_TOL, c64_bound, gate_ks
+from workloads import (Gate, ghz_circuit, layered_u3_cz, qft_circuit, random_mixed_circuit,
+                       random_pauli_sum, w_circuit, uniform_stream)
+
+pytestmark = pytest.mark.gpu
+
+qvm = pytest.importorskip("paper_2212_14201_amd.qvm")
+
+
+@pytest.fixture(autouse=True)
+def _gpu(require_gpu):
+    pass
+
+
+def tol(dtype, gates):
+    return C128_TOL if dtype == "c128" else c64_bound(gate_ks(gates))
+
+
+def run_gpu(n, gates, dtype, init=0):
+    sv = qvm.StateVector(n, dtype, init=init)
+    sv.run(gates)
+    return sv
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (5, 2), (10, 3), (13, 4), (16, 5)])
+def test_random_mixed_circuits(n, seed, dtype):
+    gates = random_mixed_circuit(n, 80, seed, kmax=min(3, n), max_ctrl=min(2, max(0, n - 3)))
+    sv = run_gpu(n, gates, dtype, init=seed % (1 << n))
+    want = oracle.simulate(n, gates, init=seed % (1 << n))
+    got = sv.amplitudes()
+    err = np.max(np.abs(got - want))
+    print(f"n={n} seed={seed} {dtype} gates={len(gates)} err={err:.3e}")
+    assert err <= tol(dtype, gates)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_many_controls_and_every_target_position(dtype):
+    n = 14
+    gates = []
+    rng = np.random.default_rng(0)
+    for t in range(n):
+        ctrls = tuple(int(c) for c in rng.choice([q for q in range(n) if q != t], 5, replace=False))
+        gates.append(Gate("h", (t,)))
+        gates.append(Gate("u3", (t,), ctrls, tuple(rng.uniform(0, 6, 3))))
+        gates.append(Gate("x", (t,), ctrls[:3]))
+        gates.append(Gate("rz", (t,), ctrls[:2], (float(rng.uniform(0, 6)),)))
+        gates.append(Gate("p", (t,), ctrls[:4], (float(rng.uniform(0, 6)),)))
+    gates.append(Gate("x", (0,), tuple(range(1, n))))          # 13-control X
+    gates.append(Gate("z", (n - 1,), tuple(range(n - 1))))    # 13-control Z
+    sv = run_gpu(n, gates, dtype)
+    want = oracle.simulate(n, gates)
+    assert np.max(np.abs(sv.amplitudes() - want)) <= tol(dtype, gates)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_three_qubit_unitaries_unsorted_targets(dtype):
+    n = 12
+    gates = random_mixed_circuit(n, 40, 77, kmax=3, max_ctrl=3, names=["unitary", "swap", "rzz"])
+    sv = run_gpu(n, gates, dtype)
+    want = oracle.simulate(n, gates)
+    assert np.max(np.abs(sv.amplitudes() - want)) <= tol(dtype, gates)
+
+
+def test_closed_forms_on_gpu():
+    for n in (3, 11):
+        sv = run_gpu(n, ghz_circuit(n), "c128")
+        a = sv.amplitudes()
+        want = np.zeros(1 << n, complex)
+        want[0] = want[-1] = 1 / math.sqrt(2)
+        assert np.max(np.abs(a - want)) < 1e-15
+        sv = run_gpu(n, w_circuit(n), "c128")
+        want = np.zeros(1 << n, complex)
+        for q in range(n):
+            want[1 << q] = 1 / math.sqrt(n)
+        assert np.max(np.abs(sv.amplitudes() - want)) < 1e-14
+    n, x = 16, 40503
+    sv = run_gpu(n, qft_circuit(n), "c128", init=x)
+    y = np.arange(1 << n)
+    want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    assert np.max(np.abs(sv.amplitudes() - want)) < 1e-12
+
+
+def test_layered_12_qubit_workload_c128():
+    """12 qubits, complex128, 20 layers of U3 + CZ brick from |0..0>:
+    amplitudes, all probabilities and every <Z_i>."""
+    n = 12
+    gates = layered_u3_cz(n, 20, 1201)
+    assert len(gates) == 350
+    sv = run_gpu(n, gates, "c128")
+    want = oracle.simulate(n, gates)
+    assert np.max(np.abs(sv.amplitudes() - want)) <= C128_TOL
+    p = sv.probabilities()
+    assert np.max(np.abs(p - oracle.probabilities(want))) <= 1e-15
+    z = sv.expect_z_all()
+    assert np.max(np.abs(z - oracle.expect_z_all(want))) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_readouts(dtype):
+    n = 15
+    gates = layered_u3_cz(n, 6, 9)
+    sv = run_gpu(n, gates, dtype)
+    psi = oracle.simulate(n, gates)
+    t = tol(dtype, gates)
+    amp = sv.amplitudes()
+    assert np.max(np.abs(amp - psi)) <= t
+    # probabilities bounded by the amplitude error
+    dp = np.abs(amp) * 0 + t * (2 * np.abs(psi) + t)
+    assert np.all(np.abs(sv.probabilities() - oracle.probabilities(psi)) <= dp + 1e-16)
+    for qs in ([0], [14], [3, 7], [9, 2, 5], list(range(0, 15, 2)), [13, 1, 0, 4, 11, 6]):
+        m = sv.probabilities(qs)
+        assert np.max(np.abs(m - oracle.marginal(psi, qs))) <= 2 * (2 * t + t * t) * 2 ** len(qs) + 1e-15
+    ptol = 2 * t + t * t if dtype == "c64" else 1e-13
+    assert np.max(np.abs(sv.expect_z_all() - oracle.expect_z_all(psi))) <= ptol * 2
+    xs, zs, cs, _ = random_pauli_sum(n, 45, 5, wmin=1, wmax=5)
+    terms, tot = sv.expect_pauli(xs, zs, cs)
+    want = np.array([oracle.expect_pauli(psi, int(x), int(z))[0] for x, z in zip(xs, zs)])
+    assert np.max(np.abs(terms - want)) <= ptol * 2
+    assert abs(tot - float(np.dot(cs, want))) <= ptol * 2 * np.sum(np.abs(cs))
+    assert abs(sv.norm() - 1.0) <= (1e-13 if dtype == "c128" else 4 * t)
+    # amplitudes by index, and a copy of a sub-range
+    idx = np.random.default_rng(1).integers(0, 1 << n, 300, dtype=np.uint64)
+    assert np.max(np.abs(sv.gather(idx) - psi[idx.astype(np.int64)])) <= t
+    assert np.max(np.abs(sv.amplitudes(1000, 77) - psi[1000:1077])) <= t
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 9, 14])
+def test_sampling(n, dtype):
+    gates = random_mixed_circuit(n, 60, 30 + n)
+    sv = run_gpu(n, gates, dtype)
+    psi = oracle.simulate(n, gates)
+    u = uniform_stream(7, 3000)
+    got = sv.sample(u).astype(np.int64)
+    want, margin = oracle.sample(psi, u)
+    want = want.astype(np.int64)
+    # samples whose target sits within the probability error of a CDF
+    # boundary may land in the neighbouring bin; all others must agree
+    t = 1e-12 if dtype == "c128" else (1 << n) * c64_bound(gate_ks(gates)) * 3
+    close = margin <= t
+    assert np.array_equal(got[~close], want[~close])
+    assert np.all(np.abs(got[close] - want[close]) <= 1)
+
+
+def test_renormalize_c64_drift():
+    n = 12
+    gates = layered_u3_cz(n, 40, 4)
+    sv = run_gpu(n, gates, "c64")
+    before = sv.renormalize()
+    assert abs(before - 1) < 1e-4
+    assert abs(sv.norm() - 1) < 1e-6
+
+
+def test_init_basis_and_determinism():
+    n = 17
+    gates = random_mixed_circuit(n, 50, 3)
+    a = run_gpu(n, gates, "c64", init=12345).amplitudes()
+    b = run_gpu(n, gates, "c64", init=12345).amplitudes()
+    assert np.array_equal(a, b)
+    sv = qvm.StateVector(n, "c128", init=(1 << n) - 1)
+    amp = sv.amplitudes()
+    assert amp[-1] == 1 and np.count_nonzero(amp) == 1
+    with pytest.raises(qvm.QvmError):
+        sv.init_basis(1 << n)
