@@ -188,6 +188,88 @@ qvm_status qvm_copy_amplitudes(qvm_sv* sv, uint64_t first, uint64_t count,
 qvm_status qvm_gather_amplitudes(qvm_sv* sv, size_t count,
                                  const uint64_t* logical_idx, double* out_host);
 
+/* --------------------------------------------------------- fused plans */
+
+/* A fused execution plan (paper, "Quantum circuit fusion": Fusion /
+ * aggregate_operations rewrites a program into unitary blocks before it is
+ * simulated; the paper leaves the algorithm open).  A plan is a list of
+ * passes.  Each pass streams every tile of 2^L amplitudes (L tile qubits,
+ * always including the lowest physical bits) through LDS once and applies a
+ * list of ops to it: fused k-qubit blocks (k = 3..6, blocks spanning fewer
+ * qubits are padded) as complex GEMMs on MFMA, and phase/diagonal gates.
+ * Controls of fused gates are folded into the block matrices; uncontrolled
+ * SWAPs become qubit relabelings.  Block matrices are built on the host in
+ * double precision and rounded to the state's dtype.  Plans are host
+ * objects; building one needs no GPU. */
+typedef struct qvm_plan qvm_plan;
+
+typedef struct qvm_plan_stats {
+    int32_t n_passes;        /* HBM round trips */
+    int32_t n_blocks;        /* fused blocks */
+    int32_t n_diag_ops;      /* standalone phase/diagonal ops */
+    int32_t tile_qubits;     /* L of the passes */
+    int32_t blocks_by_k[8];  /* blocks by the number of qubits their gates span */
+    uint64_t device_bytes;   /* size of the plan's device image */
+} qvm_plan_stats;
+
+/* Greedy planner.  k_max (1..6) bounds the qubits a fused block spans.
+ * tile_qubits = 0: every block gets its own pass ("one fused block per HBM
+ * pass"); otherwise tile_qubits in [k_max, 13] (complex64) or [k_max, 12]
+ * (complex128) and passes hold as many blocks as the tile admits.  Gate
+ * validation as in qvm_run (k <= 6); a non-diagonal gate spanning more than
+ * k_max qubits is QVM_EARG. */
+qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits,
+                           int k_max, int tile_qubits, qvm_dtype dt,
+                           qvm_plan** out);
+
+/* Plan from an explicit partition: block_of_gate[i] is the block id of gate
+ * i; blocks run in ascending id order, one pass each.  QVM_EARG if a block
+ * spans more than k_max qubits or the partition breaks the per-qubit gate
+ * order. */
+qvm_status qvm_plan_from_partition(const qvm_gate* gates, size_t n_gates,
+                                   const uint32_t* block_of_gate, int n_qubits,
+                                   int k_max, qvm_dtype dt, qvm_plan** out);
+
+qvm_status qvm_plan_info(const qvm_plan* plan, qvm_plan_stats* out);
+
+/* Block i of the plan: k (after padding), k_true, its qubits (k entries;
+ * wires, i.e. logical qubits when no relabeling SWAP precedes the block),
+ * the input indices of its gates (n_gates entries), its pass and its
+ * double-precision matrix (2^k x 2^k, (re, im), row-major; bit r <->
+ * qubits[r]).  Any output pointer may be NULL. */
+qvm_status qvm_plan_block(const qvm_plan* plan, int32_t i, int32_t* k,
+                          int32_t* k_true, int32_t* qubits, int32_t* n_gates,
+                          int32_t* gate_idx, int32_t* pass, double* m_out);
+
+/* Execution order of the input gates: exec_pos[i] = rank of gate i in the
+ * order the plan applies gates (within a block: the order its matrix
+ * multiplies them), unit_of[i] = the unit (fused block or standalone
+ * diagonal op, numbered in execution order) that applies it.  SWAPs turned
+ * into relabelings get -1 in both.  n_gates entries each; either may be
+ * NULL. */
+qvm_status qvm_plan_schedule(const qvm_plan* plan, int32_t* exec_pos,
+                             int32_t* unit_of);
+
+/* Layout the state is left in by qvm_run_plan: perm_out[q] = physical bit
+ * of logical qubit q (n entries). */
+qvm_status qvm_plan_final_layout(const qvm_plan* plan, int32_t* perm_out);
+
+/* Execute a plan on a state in the identity layout (QVM_ESTATE otherwise;
+ * see qvm_reset_layout).  Uploads the plan image into the workspace, then
+ * enqueues one tile kernel per pass.  Afterwards the state's layout is the
+ * plan's final layout; readouts account for it.  Asynchronous. */
+qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* plan);
+
+/* The plan's device image as uploaded by qvm_run_plan (for inspection and
+ * emulation): *bytes receives its size; when out is not NULL, cap >= that
+ * size bytes are copied to it.  *pass_table receives the byte offset of the
+ * pass records inside the image, *n_passes their count.  The record layouts
+ * are internal and may change between builds. */
+qvm_status qvm_plan_image(const qvm_plan* plan, void* out, size_t cap, size_t* bytes,
+                          uint64_t* pass_table, int32_t* n_passes);
+
+qvm_status qvm_plan_destroy(qvm_plan* plan);
+
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* qvm_last_error(void);
 

@@ -1,0 +1,747 @@
+// Fusion planner and plan execution (paper, "Quantum circuit fusion": the
+// Fusion / aggregate_operations step that rewrites a program into unitary
+// blocks before simulation; the paper does not specify its algorithm).
+//
+// A plan is built in three steps, all on the host in double precision:
+//  1. Wires.  Uncontrolled SWAPs become relabelings of the wires (no data
+//     movement); every later gate is rewritten onto wires.
+//  2. Passes.  Gates are scheduled over their dependency order into passes.
+//     A pass owns a tile of L physical bits that always includes the c
+//     lowest ones; a gate whose matrix is not diagonal can run in a pass
+//     only if all its qubits are tile bits, a diagonal gate can run in any
+//     pass.  In "block" mode (L = 0 requested) every fused block gets a pass
+//     of its own, i.e. one HBM round trip per block.
+//  3. Blocks.  Inside a pass, gates are fused greedily over the dependency
+//     frontier into blocks of at most k_max qubits; controls of a fused gate
+//     are folded into the block matrix.  Diagonal gates whose qubits lie
+//     outside the open block become phase/diagonal ops of their own.
+// At the end of each pass the tile bits are permuted so that the qubits
+// needed soonest sit on the low physical bits (qubit-index remapping).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "tile.hpp"
+
+namespace qvm {
+
+qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev);
+
+namespace {
+
+struct PGate {
+    int k;
+    int t[QVM_MAX_K];            // wires
+    uint64_t cmask;              // wires
+    std::vector<cd> u;           // 2^k x 2^k
+    bool diag;
+    uint64_t qmask;              // targets | controls
+    int src;                     // index in the caller's list
+};
+
+struct Unit {                    // a fused block or a standalone diagonal gate
+    bool block;
+    std::vector<int> gates;      // indices into the PGate list, in order
+    std::vector<int> qubits;     // block qubits (wires), bit r <-> qubits[r]
+};
+
+struct PassPlan {
+    std::vector<Unit> units;
+};
+
+std::atomic<uint64_t> g_plan_ids{1};
+
+}  // namespace
+}  // namespace qvm
+
+struct qvm_plan {
+    int n;
+    qvm_dtype dt;
+    int k_max;
+    int tile_qubits;
+    std::vector<char> blob;                 // device image
+    std::vector<qvm::PassDesc> passes;
+    std::vector<int> final_perm;            // logical qubit -> physical bit after the plan
+    std::vector<uint32_t> block_of_gate;    // pass-ordered block id per input gate (-1: diag op)
+    std::vector<int32_t> exec_pos;          // rank of each input gate in execution order (-1: relabel)
+    std::vector<int32_t> unit_of;           // unit (block or diagonal op) of each input gate
+    struct Block {
+        std::vector<int> qubits;            // wires (logical qubits when no SWAP precedes), padded to >= 3
+        int k_true;                         // qubits spanned by the block's gates
+        std::vector<int> gates;             // input gate indices
+        std::vector<qvm::cd> m;             // FP64 block matrix
+        int pass;
+    };
+    std::vector<Block> blocks;
+    int n_diag_ops;
+    uint64_t id;
+    uint64_t pass_table;                    // offset of the PassDesc table in the blob
+};
+
+namespace qvm {
+namespace {
+
+// y = G x for one gate on a small register (block-local bit positions).
+void apply_small(std::vector<cd>& v, int k_reg, const cd* u, int k, const int* pos, uint64_t cm) {
+    const uint64_t N = 1ull << k_reg;
+    const int dim = 1 << k;
+    uint64_t tm = 0;
+    for (int r = 0; r < k; ++r) tm |= 1ull << pos[r];
+    cd in[64];
+    uint64_t idx[64];
+    for (uint64_t b = 0; b < N; ++b) {
+        if ((b & tm) || ((b & cm) != cm)) continue;
+        for (int j = 0; j < dim; ++j) {
+            uint64_t o = b;
+            for (int r = 0; r < k; ++r)
+                if ((j >> r) & 1) o |= 1ull << pos[r];
+            idx[j] = o;
+            in[j] = v[o];
+        }
+        for (int i = 0; i < dim; ++i) {
+            cd s = 0;
+            for (int j = 0; j < dim; ++j) s += u[i * dim + j] * in[j];
+            v[idx[i]] = s;
+        }
+    }
+}
+
+// FP64 block matrix over `qubits` (bit r <-> qubits[r]) of the listed gates.
+std::vector<cd> block_matrix(const std::vector<PGate>& G, const std::vector<int>& gates,
+                             const std::vector<int>& qubits) {
+    const int k = (int)qubits.size();
+    const int dim = 1 << k;
+    std::vector<cd> M((size_t)dim * dim, cd(0, 0));
+    std::map<int, int> pos;
+    for (int r = 0; r < k; ++r) pos[qubits[r]] = r;
+    std::vector<cd> col(dim);
+    for (int c = 0; c < dim; ++c) {
+        std::fill(col.begin(), col.end(), cd(0, 0));
+        col[c] = 1.0;
+        for (int gi : gates) {
+            const PGate& g = G[gi];
+            int p[QVM_MAX_K];
+            for (int r = 0; r < g.k; ++r) p[r] = pos.at(g.t[r]);
+            uint64_t cm = 0;
+            for (int q = 0; q < 64; ++q)
+                if ((g.cmask >> q) & 1) cm |= 1ull << pos.at(q);
+            apply_small(col, k, g.u.data(), g.k, p, cm);
+        }
+        for (int r = 0; r < dim; ++r) M[(size_t)r * dim + c] = col[r];
+    }
+    return M;
+}
+
+inline int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+// Dependency tracking over a gate subset: a gate is ready when every earlier
+// gate (in the subset) sharing a qubit with it has been consumed.
+struct Frontier {
+    std::vector<std::vector<int>> per_q;     // per wire: gate indices in order
+    std::vector<size_t> ptr;
+    Frontier(int nq, const std::vector<PGate>& G, const std::vector<int>& subset)
+        : per_q(nq), ptr(nq, 0) {
+        for (int gi : subset)
+            for (int q = 0; q < nq; ++q)
+                if ((G[gi].qmask >> q) & 1) per_q[q].push_back(gi);
+    }
+    bool ready(const PGate& g, int gi) const {
+        for (uint64_t m = g.qmask; m; m &= m - 1) {
+            int q = __builtin_ctzll(m);
+            if (ptr[q] >= per_q[q].size() || per_q[q][ptr[q]] != gi) return false;
+        }
+        return true;
+    }
+    void consume(const PGate& g) {
+        for (uint64_t m = g.qmask; m; m &= m - 1) ++ptr[__builtin_ctzll(m)];
+    }
+};
+
+// Greedy frontier fusion of an ordered gate subset into units.
+std::vector<Unit> fuse(const std::vector<PGate>& G, const std::vector<int>& subset, int nq,
+                       int k_max, uint64_t allowed) {
+    std::vector<Unit> out;
+    Frontier F(nq, G, subset);
+    std::vector<char> done(subset.size(), 0);
+    size_t left = subset.size();
+    Unit cur{true, {}, {}};
+    uint64_t S = 0;
+    auto close = [&]() {
+        if (!cur.gates.empty()) {
+            for (int q = 0; q < nq; ++q)
+                if ((S >> q) & 1) cur.qubits.push_back(q);
+            out.push_back(cur);
+        }
+        cur = Unit{true, {}, {}};
+        S = 0;
+    };
+    size_t first = 0;
+    while (left) {
+        bool progress = false;
+        while (first < subset.size() && done[first]) ++first;
+        for (size_t i = first; i < subset.size(); ++i) {
+            if (done[i]) continue;
+            const int gi = subset[i];
+            const PGate& g = G[gi];
+            if (!F.ready(g, gi)) continue;
+            bool take = false;
+            if (g.diag) {
+                if (!cur.gates.empty() && (g.qmask & ~S) == 0) {
+                    cur.gates.push_back(gi);
+                    take = true;
+                } else if ((g.qmask & S) == 0) {
+                    out.push_back(Unit{false, {gi}, {}});
+                    take = true;
+                }
+            } else if (popc(S | g.qmask) <= k_max && (g.qmask & ~allowed) == 0) {
+                cur.gates.push_back(gi);
+                S |= g.qmask;
+                take = true;
+            }
+            if (take) {
+                F.consume(g);
+                done[i] = 1;
+                --left;
+                progress = true;
+            }
+        }
+        if (!progress) {
+            if (cur.gates.empty()) {
+                // a diagonal gate that overlaps nothing open is always takeable,
+                // so an empty block without progress cannot happen; guard anyway
+                break;
+            }
+            close();
+        }
+    }
+    close();
+    return out;
+}
+
+struct Builder {
+    int n;
+    qvm_dtype dt;
+    int c;            // low bits always in the tile
+    int L;            // tile bits per pass
+    std::vector<char>& blob;
+    explicit Builder(std::vector<char>& b) : blob(b) {}
+    size_t put(const void* p, size_t bytes) {
+        size_t off = (blob.size() + 255) & ~size_t(255);
+        blob.resize(off + bytes);
+        memcpy(blob.data() + off, p, bytes);
+        return off;
+    }
+};
+
+// Real MFMA fragments of a complex 2^k x 2^k matrix: K = 2^(k+1);
+// fragment (rb, s), lane l holds Mr[16 rb + l % 16][4 s + l / 16] with
+// Mr = [[Re, -Im], [Im, Re]] per complex entry.
+template <typename R>
+std::vector<R> fragments(const std::vector<cd>& M, int k) {
+    const int dim = 1 << k, K = 2 * dim, RB = K / 16, KS = K / 4;
+    auto mr = [&](int i, int j) -> double {
+        cd v = M[(size_t)(i >> 1) * dim + (j >> 1)];
+        int a = i & 1, b = j & 1;
+        if (a == 0 && b == 0) return v.real();
+        if (a == 0 && b == 1) return -v.imag();
+        if (a == 1 && b == 0) return v.imag();
+        return v.real();
+    };
+    std::vector<R> f((size_t)RB * KS * 64);
+    for (int rb = 0; rb < RB; ++rb)
+        for (int s = 0; s < KS; ++s)
+            for (int l = 0; l < 64; ++l)
+                f[((size_t)rb * KS + s) * 64 + l] = (R)mr(16 * rb + (l & 15), 4 * s + (l >> 4));
+    return f;
+}
+
+}  // namespace
+
+qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int k_max,
+                      int tile_qubits, const uint32_t* partition, qvm_plan** out) {
+    if (!out) return fail(QVM_EARG, "NULL out");
+    *out = nullptr;
+    if (n < 1 || n > QVM_MAX_QUBITS) return fail(QVM_EARG, "n_qubits outside 1..34");
+    if (dt != QVM_C64 && dt != QVM_C128) return fail(QVM_EARG, "unknown dtype");
+    if (ng && !gates) return fail(QVM_EARG, "NULL gate list");
+    if (k_max < 1 || k_max > 6) return fail(QVM_EARG, "k_max outside 1..6");
+    if (n < 3) return fail(QVM_EUNSUPPORTED, "fused plans need n >= 3 (blocks are padded to 3 qubits)");
+    // LDS per workgroup: the tile plus the widest block's real fragments
+    const int Lmax = dt == QVM_C64 ? 13 : (k_max >= 6 ? 11 : 12);
+    const int cdef = dt == QVM_C64 ? 4 : 3;
+    if (tile_qubits != 0 && (tile_qubits < k_max || tile_qubits > Lmax))
+        return fail(QVM_EARG, "tile_qubits must be 0 or in k_max..13 (complex64) / ..12 (complex128, 11 with k_max = 6)");
+    // ---- lower gates onto wires
+    std::vector<PGate> G;
+    G.reserve(ng);
+    std::vector<int> wire(n);
+    std::iota(wire.begin(), wire.end(), 0);
+    std::vector<int> src_of;
+    for (size_t i = 0; i < ng; ++i) {
+        qvm_status st = validate_gate(gates[i], n, true);
+        if (st) return fail(st, "gate " + std::to_string(i) + ": " + std::string(qvm_last_error()));
+        const qvm_gate& g = gates[i];
+        if (g.kind == QVM_G_SWAP && g.ctrl_mask == 0 && !partition) {
+            std::swap(wire[g.targets[0]], wire[g.targets[1]]);
+            continue;
+        }
+        PGate p{};
+        p.k = g.k;
+        p.cmask = 0;
+        p.qmask = 0;
+        for (int r = 0; r < g.k; ++r) {
+            p.t[r] = wire[g.targets[r]];
+            p.qmask |= 1ull << p.t[r];
+        }
+        for (int q = 0; q < n; ++q)
+            if ((g.ctrl_mask >> q) & 1) p.cmask |= 1ull << wire[q];
+        p.qmask |= p.cmask;
+        st = gate_matrix(g, p.u);
+        if (st) return st;
+        const int dim = 1 << p.k;
+        p.diag = true;
+        for (int r = 0; r < dim && p.diag; ++r)
+            for (int cc = 0; cc < dim; ++cc)
+                if (r != cc && p.u[(size_t)r * dim + cc] != cd(0, 0)) { p.diag = false; break; }
+        p.src = (int)i;
+        if (popc(p.qmask) > k_max && !p.diag)
+            return fail(QVM_EARG, "gate " + std::to_string(i) + " spans more than k_max qubits");
+        G.push_back(p);
+    }
+    const int ngw = (int)G.size();
+    // ---- tile geometry
+    int L = tile_qubits ? tile_qubits : Lmax;
+    if (L > n) L = n;
+    int c = std::min(cdef, L);
+    if (L < std::min(n, std::max(k_max, 3)))
+        return fail(QVM_EARG, "tile too small for k_max");
+
+    // ---- units for block / partition modes (one pass per block)
+    std::vector<int> all(ngw);
+    std::iota(all.begin(), all.end(), 0);
+    std::vector<Unit> units;
+    if (partition) {
+        std::map<uint32_t, std::vector<int>> byid;
+        for (int gi = 0; gi < ngw; ++gi) byid[partition[G[gi].src]].push_back(gi);
+        for (auto& kv : byid) {
+            uint64_t S = 0;
+            for (int gi : kv.second) S |= G[gi].qmask;
+            if (popc(S) > k_max) return fail(QVM_EARG, "partition block spans more than k_max qubits");
+            Unit u{true, kv.second, {}};
+            for (int q = 0; q < n; ++q)
+                if ((S >> q) & 1) u.qubits.push_back(q);
+            units.push_back(u);
+        }
+        std::vector<int> order(ngw);
+        int t = 0;
+        for (auto& u : units)
+            for (int gi : u.gates) order[gi] = t++;
+        std::vector<int> last(n, -1);
+        for (int gi = 0; gi < ngw; ++gi)
+            for (int q = 0; q < n; ++q)
+                if ((G[gi].qmask >> q) & 1) {
+                    if (last[q] >= 0 && order[last[q]] > order[gi])
+                        return fail(QVM_EARG, "partition breaks the gate order on qubit " + std::to_string(q));
+                    last[q] = gi;
+                }
+    } else if (tile_qubits == 0) {
+        units = fuse(G, all, n, k_max, ~0ull);
+    }
+    const bool tile_mode = !partition && tile_qubits != 0;
+    size_t next_unit = 0;
+
+    // ---- schedule, fuse and emit passes
+    qvm_plan* P = new (std::nothrow) qvm_plan();
+    if (!P) return fail(QVM_ENOMEM, "host allocation failed");
+    P->n = n;
+    P->dt = dt;
+    P->k_max = k_max;
+    P->tile_qubits = tile_qubits;
+    P->n_diag_ops = 0;
+    P->id = g_plan_ids.fetch_add(1);
+    P->block_of_gate.assign(ng, 0xffffffffu);
+    P->exec_pos.assign(ng, -1);
+    P->unit_of.assign(ng, -1);
+    int32_t exec_counter = 0, unit_counter = 0;
+    Builder B(P->blob);
+    std::vector<int> pos(n), at(n);      // wire -> physical bit, physical bit -> wire
+    std::iota(pos.begin(), pos.end(), 0);
+    std::iota(at.begin(), at.end(), 0);
+    Frontier F(n, G, all);
+    std::vector<char> done(ngw, 0);
+    int left = ngw;
+    int first = 0;
+    auto fail_plan = [&](qvm_status st, const std::string& m) {
+        delete P;
+        return fail(st, m);
+    };
+    while (tile_mode ? left > 0 : next_unit < units.size()) {
+        PassPlan pp;
+        uint64_t T = 0;
+        for (int b = 0; b < c; ++b) T |= 1ull << at[b];
+        if (tile_mode) {
+            std::vector<int> taken;
+            bool progress = true;
+            while (progress) {
+                progress = false;
+                while (first < ngw && done[first]) ++first;
+                for (int gi = first; gi < ngw; ++gi) {
+                    if (done[gi] || !F.ready(G[gi], gi)) continue;
+                    uint64_t need = G[gi].diag ? 0 : G[gi].qmask;
+                    if (popc(T | need) > L) continue;
+                    T |= need;
+                    F.consume(G[gi]);
+                    done[gi] = 1;
+                    --left;
+                    taken.push_back(gi);
+                    progress = true;
+                }
+            }
+            if (taken.empty()) return fail_plan(QVM_EARG, "planner made no progress");
+            // fill the tile up to L with the wires needed soonest
+            std::vector<std::pair<int, int>> nxt;
+            for (int q = 0; q < n; ++q) {
+                if ((T >> q) & 1) continue;
+                int when = ngw;
+                for (int gi = first; gi < ngw; ++gi)
+                    if (!done[gi] && !G[gi].diag && ((G[gi].qmask >> q) & 1)) { when = gi; break; }
+                nxt.push_back({when, q});
+            }
+            std::sort(nxt.begin(), nxt.end());
+            for (auto& w : nxt) {
+                if (popc(T) >= L) break;
+                T |= 1ull << w.second;
+            }
+            pp.units = fuse(G, taken, n, k_max, T);
+        } else {
+            // diagonal units ride in the pass of the next block
+            while (next_unit < units.size()) {
+                pp.units.push_back(units[next_unit++]);
+                if (pp.units.back().block) break;
+            }
+            for (auto& u : pp.units)
+                if (u.block)
+                    for (int q : u.qubits) T |= 1ull << q;
+            if (popc(T) > L) return fail_plan(QVM_EARG, "block does not fit the tile");
+            for (int b = c; b < n && popc(T) < L; ++b) T |= 1ull << at[b];
+        }
+        // local bit of each tile wire: ascending physical bit (the c low
+        // physical bits come first)
+        std::vector<int> phys;
+        for (int q = 0; q < n; ++q)
+            if ((T >> q) & 1) phys.push_back(pos[q]);
+        std::sort(phys.begin(), phys.end());
+        if ((int)phys.size() != L) return fail_plan(QVM_EARG, "internal: tile size mismatch");
+        for (int b = 0; b < c; ++b)
+            if (phys[b] != b) return fail_plan(QVM_EARG, "internal: low bits missing from the tile");
+        std::vector<int> local_of_wire(n, -1);
+        uint64_t qmask = 0;
+        for (int i = 0; i < L; ++i) {
+            local_of_wire[at[phys[i]]] = i;
+            qmask |= 1ull << phys[i];
+        }
+        const int pi = (int)P->passes.size();
+        std::vector<TOp> ops;
+        std::vector<DSub> run;
+        auto flush = [&]() {
+            if (run.empty()) return;
+            TOp op{};
+            op.type = TOP_DIAGRUN;
+            op.k = (int32_t)run.size();
+            op.data = B.put(run.data(), run.size() * sizeof(DSub));
+            ops.push_back(op);
+            run.clear();
+        };
+        for (auto& u : pp.units) {
+            TOp op{};
+            for (int gi : u.gates) {
+                P->exec_pos[G[gi].src] = exec_counter++;
+                P->unit_of[G[gi].src] = unit_counter;
+            }
+            ++unit_counter;
+            if (u.block) {
+                flush();
+                std::vector<int> bq = u.qubits;
+                const int k_true = (int)bq.size();
+                for (int i = 0; (int)bq.size() < 3 && i < L; ++i) {
+                    int w = at[phys[i]];
+                    if (std::find(bq.begin(), bq.end(), w) == bq.end()) bq.push_back(w);
+                }
+                const int k = (int)bq.size();
+                std::vector<cd> M = block_matrix(G, u.gates, bq);
+                op.type = TOP_BLOCK;
+                op.k = k;
+                for (int r = 0; r < k; ++r) op.lb[r] = local_of_wire[bq[r]];
+                if (dt == QVM_C64) {
+                    auto f = fragments<float>(M, k);
+                    op.data = B.put(f.data(), f.size() * sizeof(float));
+                } else {
+                    auto f = fragments<double>(M, k);
+                    op.data = B.put(f.data(), f.size() * sizeof(double));
+                }
+                qvm_plan::Block blk;
+                blk.qubits = bq;
+                blk.k_true = k_true;
+                for (int gi : u.gates) {
+                    blk.gates.push_back(G[gi].src);
+                    P->block_of_gate[G[gi].src] = (uint32_t)P->blocks.size();
+                }
+                blk.m = std::move(M);
+                blk.pass = pi;
+                P->blocks.push_back(std::move(blk));
+            } else {
+                // diagonal gate -> phase terms over its target patterns
+                const PGate& g = G[u.gates[0]];
+                uint64_t tmask = 0;
+                for (int r = 0; r < g.k; ++r) tmask |= 1ull << pos[g.t[r]];
+                uint64_t pc = 0;
+                for (int q = 0; q < n; ++q)
+                    if ((g.cmask >> q) & 1) pc |= 1ull << pos[q];
+                const int dim = 1 << g.k;
+                for (int j = 0; j < dim; ++j) {
+                    const cd v = g.u[(size_t)j * dim + j];
+                    if (v == cd(1, 0)) continue;
+                    uint64_t pv = pc;
+                    for (int r = 0; r < g.k; ++r)
+                        if ((j >> r) & 1) pv |= 1ull << pos[g.t[r]];
+                    const uint64_t pm = pc | tmask;
+                    DSub d{};
+                    d.omask = pm & ~qmask;
+                    d.oval = pv & ~qmask;
+                    for (int i = 0; i < L; ++i) {
+                        if ((pm >> phys[i]) & 1) d.lmask |= 1u << i;
+                        if ((pv >> phys[i]) & 1) d.lval |= 1u << i;
+                    }
+                    d.neg = v == cd(-1, 0);
+                    d.pr = v.real();
+                    d.pi = v.imag();
+                    run.push_back(d);
+                }
+                P->n_diag_ops++;
+                continue;
+            }
+            ops.push_back(op);
+        }
+        flush();
+        PassDesc pd{};
+        pd.L = L;
+        pd.c = c;
+        pd.nops = (int)ops.size();
+        pd.kmax = 0;
+        for (const TOp& o : ops)
+            if (o.type == TOP_BLOCK && o.k > pd.kmax) pd.kmax = o.k;
+        pd.qmask = qmask;
+        pd.ops = ops.empty() ? 0 : B.put(ops.data(), ops.size() * sizeof(TOp));
+        std::vector<uint64_t> ldoff((size_t)1 << (L - c));
+        for (size_t ch = 0; ch < ldoff.size(); ++ch) {
+            uint64_t off = 0;
+            for (int i = c; i < L; ++i)
+                if ((ch >> (i - c)) & 1) off |= 1ull << phys[i];
+            ldoff[ch] = off;
+        }
+        pd.ldoff = B.put(ldoff.data(), ldoff.size() * sizeof(uint64_t));
+        // ---- remap: put the tile wires needed soonest on the low physical bits
+        pd.remap = 0;
+        const bool more = tile_mode ? left > 0 : next_unit < units.size();
+        if (more && c > 0 && L > c) {
+            std::vector<int> nextu(n, 1 << 30);
+            if (tile_mode) {
+                for (int gi = first; gi < ngw; ++gi)
+                    if (!done[gi] && !G[gi].diag)
+                        for (uint64_t m = G[gi].qmask; m; m &= m - 1) {
+                            int q = __builtin_ctzll(m);
+                            if (nextu[q] > gi) nextu[q] = gi;
+                        }
+            } else {
+                for (size_t ui = next_unit; ui < units.size(); ++ui)
+                    if (units[ui].block)
+                        for (int q : units[ui].qubits)
+                            if (nextu[q] > (int)ui) nextu[q] = (int)ui;
+            }
+            std::vector<int> tw(L);
+            for (int i = 0; i < L; ++i) tw[i] = at[phys[i]];
+            std::vector<int> want = tw;
+            std::stable_sort(want.begin(), want.end(), [&](int a, int b) { return nextu[a] < nextu[b]; });
+            want.resize(c);
+            auto wanted = [&](int w) { return std::find(want.begin(), want.end(), w) != want.end(); };
+            std::vector<int> newat(L, -1);          // destination slot -> wire
+            std::vector<char> placed(n, 0);
+            for (int i = 0; i < c; ++i)
+                if (wanted(tw[i])) {
+                    newat[i] = tw[i];
+                    placed[tw[i]] = 1;
+                }
+            for (int w : want)
+                if (!placed[w])
+                    for (int i = 0; i < c; ++i)
+                        if (newat[i] < 0) {
+                            newat[i] = w;
+                            placed[w] = 1;
+                            break;
+                        }
+            for (int i = c; i < L; ++i)
+                if (!placed[tw[i]]) {
+                    newat[i] = tw[i];
+                    placed[tw[i]] = 1;
+                }
+            for (int i = 0; i < c; ++i)
+                if (!placed[tw[i]])
+                    for (int j = c; j < L; ++j)
+                        if (newat[j] < 0) {
+                            newat[j] = tw[i];
+                            placed[tw[i]] = 1;
+                            break;
+                        }
+            bool ident = true;
+            for (int i = 0; i < L; ++i)
+                if (newat[i] != tw[i]) ident = false;
+            if (!ident) {
+                // destination slot d receives wire newat[d], found at local
+                // slot src[d] of the loaded tile
+                std::vector<int> src(L);
+                for (int d = 0; d < L; ++d) src[d] = local_of_wire[newat[d]];
+                std::vector<uint32_t> hi((size_t)1 << (L - c)), lo((size_t)1 << c);
+                for (size_t v = 0; v < hi.size(); ++v) {
+                    uint32_t e = 0;
+                    for (int d = c; d < L; ++d)
+                        if ((v >> (d - c)) & 1) e |= 1u << src[d];
+                    hi[v] = e;
+                }
+                for (size_t v = 0; v < lo.size(); ++v) {
+                    uint32_t e = 0;
+                    for (int d = 0; d < c; ++d)
+                        if ((v >> d) & 1) e |= 1u << src[d];
+                    lo[v] = e;
+                }
+                pd.remap = 1;
+                pd.rmhi = B.put(hi.data(), hi.size() * sizeof(uint32_t));
+                pd.rmlo = B.put(lo.data(), lo.size() * sizeof(uint32_t));
+                for (int d = 0; d < L; ++d) {
+                    pos[newat[d]] = phys[d];
+                    at[phys[d]] = newat[d];
+                }
+            }
+        }
+        P->passes.push_back(pd);
+    }
+    P->final_perm.resize(n);
+    for (int l = 0; l < n; ++l) P->final_perm[l] = pos[wire[l]];
+    P->pass_table = P->passes.empty() ? 0 : B.put(P->passes.data(), P->passes.size() * sizeof(PassDesc));
+    *out = P;
+    return QVM_OK;
+}
+
+qvm_status run_plan(qvm_sv* sv, const qvm_plan* P) {
+    for (int q = 0; q < sv->n; ++q)
+        if (sv->perm[q] != q) return fail(QVM_ESTATE, "run_plan needs the identity layout; call qvm_reset_layout");
+    if (P->blob.size() > sv->lay.plan_bytes) return fail(QVM_ENOMEM, "plan data exceeds the workspace plan area");
+    char* dblob = sv->work + sv->lay.plan_off;
+    if (!P->blob.empty())
+        QVM_HIP(sv, hipMemcpyAsync(dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice, sv->stream));
+    for (const PassDesc& pd : P->passes) {
+        qvm_status st = launch_tile_pass(sv, pd, dblob);
+        if (st) return st;
+    }
+    for (int q = 0; q < sv->n; ++q) sv->perm[q] = P->final_perm[q];
+    return QVM_OK;
+}
+
+}  // namespace qvm
+
+using namespace qvm;
+
+extern "C" {
+
+qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits, int k_max,
+                           int tile_qubits, qvm_dtype dt, qvm_plan** out) {
+    return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out);
+}
+
+qvm_status qvm_plan_from_partition(const qvm_gate* gates, size_t n_gates, const uint32_t* block_of_gate,
+                                   int n_qubits, int k_max, qvm_dtype dt, qvm_plan** out) {
+    if (n_gates && !block_of_gate) return fail(QVM_EARG, "NULL partition");
+    return build_plan(gates, n_gates, n_qubits, dt, k_max, 0, block_of_gate, out);
+}
+
+qvm_status qvm_plan_image(const qvm_plan* p, void* out, size_t cap, size_t* bytes,
+                          uint64_t* pass_table, int32_t* n_passes) {
+    if (!p) return fail(QVM_EARG, "NULL plan");
+    if (bytes) *bytes = p->blob.size();
+    if (pass_table) *pass_table = p->pass_table;
+    if (n_passes) *n_passes = (int32_t)p->passes.size();
+    if (out) {
+        if (cap < p->blob.size()) return fail(QVM_ENOMEM, "buffer too small for the plan image");
+        memcpy(out, p->blob.data(), p->blob.size());
+    }
+    return QVM_OK;
+}
+
+qvm_status qvm_plan_destroy(qvm_plan* p) {
+    delete p;
+    return QVM_OK;
+}
+
+qvm_status qvm_plan_info(const qvm_plan* p, qvm_plan_stats* s) {
+    if (!p || !s) return fail(QVM_EARG, "NULL argument");
+    memset(s, 0, sizeof(*s));
+    s->n_passes = (int32_t)p->passes.size();
+    s->n_blocks = (int32_t)p->blocks.size();
+    s->n_diag_ops = p->n_diag_ops;
+    for (auto& b : p->blocks) s->blocks_by_k[b.k_true]++;
+    s->tile_qubits = p->passes.empty() ? 0 : p->passes[0].L;
+    s->device_bytes = p->blob.size();
+    return QVM_OK;
+}
+
+qvm_status qvm_plan_block(const qvm_plan* p, int32_t i, int32_t* k, int32_t* k_true, int32_t* qubits,
+                          int32_t* n_gates, int32_t* gate_idx, int32_t* pass, double* m_out) {
+    if (!p) return fail(QVM_EARG, "NULL plan");
+    if (i < 0 || i >= (int)p->blocks.size()) return fail(QVM_ERANGE, "block index out of range");
+    const auto& b = p->blocks[i];
+    if (k) *k = (int32_t)b.qubits.size();
+    if (k_true) *k_true = b.k_true;
+    if (qubits)
+        for (size_t r = 0; r < b.qubits.size(); ++r) qubits[r] = b.qubits[r];
+    if (n_gates) *n_gates = (int32_t)b.gates.size();
+    if (gate_idx)
+        for (size_t r = 0; r < b.gates.size(); ++r) gate_idx[r] = b.gates[r];
+    if (pass) *pass = b.pass;
+    if (m_out)
+        for (size_t r = 0; r < b.m.size(); ++r) {
+            m_out[2 * r] = b.m[r].real();
+            m_out[2 * r + 1] = b.m[r].imag();
+        }
+    return QVM_OK;
+}
+
+qvm_status qvm_plan_schedule(const qvm_plan* p, int32_t* exec_pos, int32_t* unit_of) {
+    if (!p) return fail(QVM_EARG, "NULL plan");
+    for (size_t i = 0; i < p->exec_pos.size(); ++i) {
+        if (exec_pos) exec_pos[i] = p->exec_pos[i];
+        if (unit_of) unit_of[i] = p->unit_of[i];
+    }
+    return QVM_OK;
+}
+
+qvm_status qvm_plan_final_layout(const qvm_plan* p, int32_t* perm_out) {
+    if (!p || !perm_out) return fail(QVM_EARG, "NULL argument");
+    for (int q = 0; q < p->n; ++q) perm_out[q] = p->final_perm[q];
+    return QVM_OK;
+}
+
+qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* p) {
+    if (!sv || !p) return fail(QVM_EARG, "NULL argument");
+    if (sv->failed) return fail(QVM_ESTATE, "state handle failed earlier");
+    if (p->n != sv->n || p->dt != sv->dt) return fail(QVM_EARG, "plan built for another n or dtype");
+    return run_plan(sv, p);
+}
+
+}  // extern "C"

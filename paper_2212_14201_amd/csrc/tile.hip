@@ -1,0 +1,369 @@
+// Tile kernel: one pass of a fused plan.
+//
+// Each workgroup owns one tile: the 2^L amplitudes that share the values of
+// all non-tile physical bits.  The tile always contains the lowest c
+// physical bits, so it is read and written as runs of 2^c contiguous
+// amplitudes (128 bytes).  The tile is staged in LDS, the pass's ops run on
+// it in order, and it is written back, optionally with its tile bits
+// permuted (qubit-index remapping at no extra traffic).
+//
+// Ops:
+//   TOP_BLOCK  a fused k-qubit block (k = 3..6): Y = M X over the tile's
+//              2^(L-k) columns, as a real GEMM on MFMA 16x16x4 (FP32 for
+//              complex64, FP64 for complex128).  The complex matrix M is
+//              expanded to the real 2^(k+1) x 2^(k+1) matrix
+//              [[Re, -Im], [Im, Re]] per entry, so interleaved (re, im)
+//              amplitudes are used as they are stored.
+//   TOP_DIAGRUN  a run of diagonal gates (CZ, CR, S, T, RZ, RZZ, controlled
+//              phases), each as phase terms on bit patterns over tile bits
+//              and the tile's fixed outer bits, applied with the tile
+//              elements held in registers.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "tile.hpp"
+
+namespace qvm {
+
+constexpr int NT = 512;               // threads per tile workgroup (8 waves)
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct TT;
+// Output layout of the 16x16x4 MFMA: register r of lane l holds column
+// l % 16 and a row that differs between the FP32 and FP64 instructions
+// (checked on gfx950): FP32 rows 4 (l / 16) + r, FP64 rows l / 16 + 4 r.
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+typedef double f64v2 __attribute__((ext_vector_type(2)));
+template <> struct TT<float> {
+    using V4 = f32x4;
+    using V16 = f32v4;                // one 16-byte access: two complex64
+    static constexpr int EP = 2;      // elements per 16-byte access
+    static constexpr int C = 4;       // low bits per tile: 16 x 8 B = 128-byte runs
+    static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
+};
+template <> struct TT<double> {
+    using V4 = f64x4;
+    using V16 = f64v2;                // one 16-byte access: one complex128
+    static constexpr int EP = 1;
+    static constexpr int C = 3;       // low bits per tile: 8 x 16 B = 128-byte runs
+    static __device__ __forceinline__ int out_row(int g, int r) { return g + 4 * r; }
+};
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// LDS slot of tile element e: bits 1..3 are XOR-ed with bits 4..6 and 8..10
+// so that column walks with large strides spread over banks; bit 0 is kept,
+// so pairs (2m, 2m+1) stay adjacent for 16-byte accesses.
+__device__ __forceinline__ uint32_t sw(uint32_t e) {
+    return e ^ ((((e >> 4) ^ (e >> 8)) & 7u) << 1);
+}
+
+__device__ __forceinline__ uint32_t dep32(uint32_t w, uint32_t fixed) {
+    while (fixed) {
+        uint32_t low = fixed & (~fixed + 1);
+        uint32_t lo = w & (low - 1);
+        w = ((w - lo) << 1) | lo;
+        fixed ^= low;
+    }
+    return w;
+}
+
+__device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
+    while (fixed) {
+        uint64_t low = fixed & (~fixed + 1);
+        uint64_t lo = w & (low - 1);
+        w = ((w - lo) << 1) | lo;
+        fixed ^= low;
+    }
+    return w;
+}
+
+// ---------------------------------------------------------------- blocks
+// The block's real fragments are first copied into LDS (after the tile);
+// every k-step then reads one A value per row block and one B value per
+// column tile from LDS.  Fragment (rb, s), lane l holds
+// Mr[16 rb + l % 16][4 s + l / 16]; B feeds X rows 4 s + l / 16 of column
+// l % 16; the 16x16 result leaves rows 4 (l / 16) + r of column l % 16 in
+// lane l.  Each wave owns whole columns, so the in-place update needs no
+// barrier between its reads and writes.
+template <typename R, int K>
+__device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ ldsA, const TOp& op,
+                                        const char* __restrict__ blob, int L) {
+    using V4 = typename TT<R>::V4;
+    constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
+    constexpr int KS = K / 4;                  // k-steps of 4 real rows
+    constexpr int k = K == 16 ? 3 : K == 32 ? 4 : K == 64 ? 5 : 6;
+    constexpr int CT = RB >= 4 ? 1 : 4 / RB;   // column tiles per wave iteration
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = NT / 64;
+    {
+        const R* __restrict__ frag = (const R*)(blob + op.data);
+        for (int i = threadIdx.x; i < K * K; i += NT) ldsA[i] = frag[i];
+    }
+    __syncthreads();
+    int lb[6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) lb[r] = op.lb[r];
+    uint32_t bmask = 0;
+#pragma unroll
+    for (int r = 0; r < k; ++r) bmask |= 1u << lb[r];
+    const int ncol = 1 << (L - k);
+    const int ntile = (ncol + 15) >> 4;
+    const int part = (lane >> 4) & 1;
+    const uint32_t hbit = (lane >> 5) ? (1u << lb[0]) : 0u;
+    for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
+        uint32_t eb[CT];
+        bool ok[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            int c = (t0 + ct) * 16 + (lane & 15);
+            ok[ct] = (t0 + ct) < ntile && c < ncol;
+            eb[ct] = ok[ct] ? dep32((uint32_t)c, bmask) : 0u;
+        }
+        V4 acc[CT][RB];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[ct][rb] = V4{0, 0, 0, 0};
+#pragma unroll 2
+        for (int s = 0; s < KS; ++s) {
+            uint32_t js = hbit;
+#pragma unroll
+            for (int r = 1; r < k; ++r)
+                if ((s >> (r - 1)) & 1) js |= 1u << lb[r];
+            R b[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds[2 * sw(eb[ct] | js) + part] : (R)0;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                R av = ldsA[(rb * KS + s) * 64 + lane];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) acc[ct][rb] = mfma16(av, b[ct], acc[ct][rb]);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            if (!ok[ct]) continue;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // real output row held in register r of this lane
+                    const int i = 16 * rb + TT<R>::out_row(lane >> 4, r);
+                    const int jo = i >> 1;
+                    uint32_t e = eb[ct];
+#pragma unroll
+                    for (int q = 0; q < k; ++q)
+                        if ((jo >> q) & 1) e |= 1u << lb[q];
+                    lds[2 * sw(e) + (i & 1)] = acc[ct][rb][r];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------- diagonal runs
+// A run of consecutive diagonal gates, each lowered to phase terms "multiply
+// by p where (index & mask) == val".  Thread t holds the tile elements
+// t + NT i in registers.  The pattern test on the bits below log2(NT)
+// depends only on t and becomes a per-lane factor chosen once per term; the
+// test on the bits above depends only on i, so it is uniform across the
+// wave and skips whole elements without divergence.
+template <typename R, int L>
+__device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __restrict__ subs,
+                                             int nsub, uint64_t base) {
+    constexpr uint32_t nE = 1u << L;
+    constexpr int NROW = nE >= NT ? (int)(nE / NT) : 1;   // elements per thread
+    constexpr int NPT = NROW < 16 ? NROW : 16;             // elements per sweep
+    constexpr uint32_t LOWM = NT - 1;
+    const uint32_t t = threadIdx.x;
+    const bool live = t < nE;
+#pragma unroll 1
+    for (int i0 = 0; i0 < NROW; i0 += NPT) {
+        R xr[NPT], xi[NPT];
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+                xr[i] = lds[s];
+                xi[i] = lds[s + 1];
+            }
+        }
+#pragma unroll 1
+        for (int q = 0; q < nsub; ++q) {
+            const DSub& d = subs[q];
+            if ((base & d.omask) != d.oval) continue;
+            const uint32_t lm = d.lmask, lv = d.lval;
+            const bool hlo = (t & lm & LOWM) == (lv & LOWM);
+            const uint32_t mhi = lm & ~LOWM, vhi = lv & ~LOWM;
+            // per-lane factor: the term's phase where the low bits match, else 1
+            const R fr = hlo ? (R)d.pr : (R)1;
+            const R fi = hlo ? (R)d.pi : (R)0;
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) {
+                    const R a = xr[i], b = xi[i];
+                    xr[i] = fr * a - fi * b;
+                    xi[i] = fr * b + fi * a;
+                }
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+                lds[s] = xr[i];
+                lds[s + 1] = xi[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernel
+template <typename R, int L>
+__global__ __launch_bounds__(NT, 1) void k_tile(R* __restrict__ psi, PassDesc pd,
+                                                 const char* __restrict__ blob) {
+    extern __shared__ __align__(16) char smem[];
+    R* lds = (R*)smem;
+    constexpr int EP = TT<R>::EP;
+    constexpr int C = TT<R>::C < L ? TT<R>::C : L;          // low bits in every tile
+    constexpr uint32_t NP = (1u << L) / EP;                  // 16-byte pieces per tile
+    constexpr int NIT = NP >= NT ? (int)(NP / NT) : 1;       // pieces per thread
+    constexpr int BATCH = NIT < 8 ? NIT : 8;
+    constexpr uint32_t CM = (1u << C) - 1;
+    using V16 = typename TT<R>::V16;
+    R* ldsA = lds + (2u << L);               // block fragments follow the tile
+    const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
+    const uint64_t* __restrict__ ldoff = (const uint64_t*)(blob + pd.ldoff);
+    const bool live = threadIdx.x < NP;
+
+    // load: per batch, all addresses first, then all loads in flight, then LDS
+    if (live) {
+#pragma unroll
+        for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+            uint64_t g[BATCH];
+            V16 v[BATCH];
+#pragma unroll
+            for (int it = 0; it < BATCH; ++it) {
+                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                g[it] = base + ldoff[e >> C] + (e & CM);
+            }
+#pragma unroll
+            for (int it = 0; it < BATCH; ++it) v[it] = *(const V16*)(psi + 2 * g[it]);
+#pragma unroll
+            for (int it = 0; it < BATCH; ++it) {
+                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                *(V16*)(lds + 2 * sw(e)) = v[it];
+            }
+        }
+    }
+    __syncthreads();
+
+    const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
+    for (int oi = 0; oi < pd.nops; ++oi) {
+        const TOp& op = ops[oi];
+        if (op.type == TOP_BLOCK) {
+            switch (op.k) {
+                case 3: tile_block<R, 16>(lds, ldsA, op, blob, L); break;
+                case 4: tile_block<R, 32>(lds, ldsA, op, blob, L); break;
+                case 5: tile_block<R, 64>(lds, ldsA, op, blob, L); break;
+                case 6: tile_block<R, 128>(lds, ldsA, op, blob, L); break;
+                default: break;
+            }
+        } else {
+            tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+        }
+        __syncthreads();
+    }
+
+    // store: per batch, LDS reads first (optionally through the tile-bit
+    // remap), then the global stores
+    if (live) {
+        const uint32_t* __restrict__ rmhi = (const uint32_t*)(blob + pd.rmhi);
+        const uint32_t* __restrict__ rmlo = (const uint32_t*)(blob + pd.rmlo);
+        const bool remap = pd.remap != 0;
+#pragma unroll
+        for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+            V16 v[BATCH];
+            if (!remap) {
+#pragma unroll
+                for (int it = 0; it < BATCH; ++it) {
+                    const uint32_t d = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                    v[it] = *(const V16*)(lds + 2 * sw(d));
+                }
+            } else {
+                // table reads first (all in flight), then the LDS gathers
+                uint32_t hi[BATCH], lo0[BATCH], lo1[BATCH];
+#pragma unroll
+                for (int it = 0; it < BATCH; ++it) {
+                    const uint32_t d = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                    hi[it] = rmhi[d >> C];
+                    lo0[it] = rmlo[d & CM];
+                    lo1[it] = EP == 2 ? rmlo[(d + 1) & CM] : 0u;
+                }
+#pragma unroll
+                for (int it = 0; it < BATCH; ++it) {
+                    const uint32_t s0 = 2 * sw(hi[it] | lo0[it]);
+                    if constexpr (EP == 2) {
+                        const uint32_t s1 = 2 * sw(hi[it] | lo1[it]);
+                        v[it] = V16{lds[s0], lds[s0 + 1], lds[s1], lds[s1 + 1]};
+                    } else {
+                        v[it] = V16{lds[s0], lds[s0 + 1]};
+                    }
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < BATCH; ++it) {
+                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                *(V16*)(psi + 2 * (base + ldoff[e >> C] + (e & CM))) = v[it];
+            }
+        }
+    }
+}
+
+size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
+    const size_t es = dt == QVM_C64 ? 4 : 8;          // bytes per real
+    const size_t K = kmax_block >= 3 ? (size_t)2 << kmax_block : 0;
+    return ((size_t)2 << L) * es + K * K * es;
+}
+
+template <typename R>
+static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, size_t lds) {
+    static bool attr_set[16] = {};
+    const unsigned grid = 1u << (sv->n - pd.L);
+    const void* fn = nullptr;
+    switch (pd.L) {
+#define QVM_TILE_CASE(LL) \
+        case LL: fn = (const void*)k_tile<R, LL>; break;
+        QVM_TILE_CASE(3) QVM_TILE_CASE(4) QVM_TILE_CASE(5) QVM_TILE_CASE(6) QVM_TILE_CASE(7)
+        QVM_TILE_CASE(8) QVM_TILE_CASE(9) QVM_TILE_CASE(10) QVM_TILE_CASE(11) QVM_TILE_CASE(12)
+        QVM_TILE_CASE(13)
+#undef QVM_TILE_CASE
+        default: return fail(QVM_EUNSUPPORTED, "tile size outside 3..13");
+    }
+    if (pd.c != (TT<R>::C < pd.L ? TT<R>::C : pd.L)) return fail(QVM_EARG, "internal: pass low-bit count");
+    if (!attr_set[pd.L]) {
+        QVM_HIP(sv, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLdsMax));
+        attr_set[pd.L] = true;
+    }
+    R* amps = (R*)sv->amps;
+    void* args[] = {(void*)&amps, (void*)&pd, (void*)&blob_dev};
+    QVM_HIP(sv, hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds, sv->stream));
+    return QVM_OK;
+}
+
+qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev) {
+    const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax);
+    if (lds > kTileLdsMax) return fail(QVM_EUNSUPPORTED, "pass needs more LDS than a workgroup has");
+    return sv->dt == QVM_C64 ? launch_tile_t<float>(sv, pd, blob_dev, lds)
+                             : launch_tile_t<double>(sv, pd, blob_dev, lds);
+}
+
+}  // namespace qvm

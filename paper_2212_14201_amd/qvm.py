@@ -294,3 +294,95 @@ class StateVector:
         check(lib().qvm_gather_amplitudes(self._h, idx.size, idx.ctypes.data_as(_u64p),
                                           out.ctypes.data_as(_dp)))
         return out.view(np.complex128)
+
+
+# ------------------------------------------------------------------ plans
+class QvmPlanStats(ctypes.Structure):
+    _fields_ = [("n_passes", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
+                ("n_diag_ops", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
+                ("blocks_by_k", ctypes.c_int32 * 8), ("device_bytes", ctypes.c_uint64)]
+
+
+def _declare_plan(L):
+    st = ctypes.c_int
+    sig = {
+        "qvm_plan_greedy": (st, [_gp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.POINTER(_vp)]),
+        "qvm_plan_from_partition": (st, [_gp, ctypes.c_size_t, _u32p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(_vp)]),
+        "qvm_plan_info": (st, [_vp, ctypes.POINTER(QvmPlanStats)]),
+        "qvm_plan_block": (st, [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, _dp]),
+        "qvm_plan_schedule": (st, [_vp, _i32p, _i32p]),
+        "qvm_plan_final_layout": (st, [_vp, _i32p]),
+        "qvm_run_plan": (st, [_vp, _vp]),
+        "qvm_plan_destroy": (st, [_vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+class Plan:
+    """A fused execution plan (host object built by the library)."""
+
+    def __init__(self, gates, n: int, dtype: str = "c64", k_max: int = 5, tile_qubits: int = 0,
+                 partition=None):
+        _declare_plan(lib())
+        self.gates = gates if isinstance(gates, GateArray) else GateArray(gates)
+        self.n = int(n)
+        self.dtype = "c64" if _dt(dtype) == QVM_C64 else "c128"
+        h = _vp()
+        if partition is None:
+            check(lib().qvm_plan_greedy(self.gates.ptr(), self.gates.n, self.n, int(k_max),
+                                        int(tile_qubits), _dt(dtype), ctypes.byref(h)))
+        else:
+            part = np.ascontiguousarray(partition, dtype=np.uint32)
+            check(lib().qvm_plan_from_partition(self.gates.ptr(), self.gates.n,
+                                                part.ctypes.data_as(_u32p), self.n, int(k_max),
+                                                _dt(dtype), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        try:
+            if self._h.value:
+                lib().qvm_plan_destroy(self._h)
+                self._h = _vp()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        s = QvmPlanStats()
+        check(lib().qvm_plan_info(self._h, ctypes.byref(s)))
+        return {"passes": s.n_passes, "blocks": s.n_blocks, "diag_ops": s.n_diag_ops,
+                "tile_qubits": s.tile_qubits, "blocks_by_k": list(s.blocks_by_k),
+                "device_bytes": int(s.device_bytes)}
+
+    def block(self, i: int) -> dict:
+        k = ctypes.c_int32()
+        kt = ctypes.c_int32()
+        ng = ctypes.c_int32()
+        ps = ctypes.c_int32()
+        check(lib().qvm_plan_block(self._h, i, ctypes.byref(k), ctypes.byref(kt), None,
+                                   ctypes.byref(ng), None, ctypes.byref(ps), None))
+        qs = np.zeros(k.value, np.int32)
+        gi = np.zeros(ng.value, np.int32)
+        m = np.zeros(2 << (2 * k.value), np.float64)
+        check(lib().qvm_plan_block(self._h, i, None, None, qs.ctypes.data_as(_i32p), None,
+                                   gi.ctypes.data_as(_i32p), None, m.ctypes.data_as(_dp)))
+        return {"k": k.value, "k_true": kt.value, "qubits": qs.tolist(), "gates": gi.tolist(),
+                "pass": ps.value, "matrix": m.view(np.complex128).reshape(1 << k.value, 1 << k.value)}
+
+    def schedule(self):
+        pos = np.zeros(self.gates.n, np.int32)
+        unit = np.zeros(self.gates.n, np.int32)
+        check(lib().qvm_plan_schedule(self._h, pos.ctypes.data_as(_i32p), unit.ctypes.data_as(_i32p)))
+        return pos, unit
+
+    def final_layout(self):
+        out = np.zeros(self.n, np.int32)
+        check(lib().qvm_plan_final_layout(self._h, out.ctypes.data_as(_i32p)))
+        return out
+
+    def run(self, sv: "StateVector"):
+        check(lib().qvm_run_plan(sv.handle, self._h))

