@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the full-amplitude state-vector hot path on one MI355X.
+
+Workload: 30 qubits, a seeded random basis state |x>, the quantum Fourier
+transform, then 30 layers of random U3 on every qubit plus a CZ brick
+(1,815 gates).  One step runs the whole path on it:
+
+  fused complex64:  plan (lowering + fusion, host) -> init |x> -> fused tile
+                    passes (MFMA blocks, diagonal runs, remapping) ->
+                    <Z_q> for all q, <Z_q Z_q+1>, an 8-qubit marginal,
+                    1,024 samples, renormalisation (FP64 readouts)
+  plain complex128: init |x> -> one kernel per gate -> <Z_q> for all q
+
+The reported value is the fused complex64 path's end-to-end gates/s
+(planning included, as the paper adds optimisation time to the total).
+Beside it: both paths' effective bandwidth, the speed-up, the dominant
+kernel's roofline fraction from live per-launch HIP events, and the FP64
+CPU oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective HBM GB/s + gates/s, 30-qubit statevector, fused c64 vs plain c128"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK = {"f32": 157.3e12, "f64": 78.6e12}
+
+
+def plain_bytes(gates, n, elem_bytes):
+    """Algorithmic bytes of the plain per-gate path: every amplitude a gate
+    changes is read and written once (dense: all; X/CNOT/SWAP moves: half;
+    phase gates: the matching quarter; 2^-c for c controls)."""
+    N = float(1 << n)
+    tot = 0.0
+    for g in gates:
+        c = len(g.controls)
+        if g.name in ("z", "s", "t", "sdg", "tdg", "p"):
+            f = 0.5 ** (1 + c)            # one phase entry on the target's 1 half
+        elif g.name == "swap":
+            f = 0.5 * 0.5 ** c
+        elif g.name == "x" and c:
+            f = 0.5 ** c                  # pairs where the controls are set
+        else:
+            f = 0.5 ** c
+        tot += 2.0 * N * elem_bytes * f
+    return tot
+
+
+def src_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "dense1": ["paper_2212_14201_amd/csrc/gates.hip"],
+    "phase": ["paper_2212_14201_amd/csrc/gates.hip"],
+    "swappair": ["paper_2212_14201_amd/csrc/gates.hip"],
+    "tile": ["paper_2212_14201_amd/csrc/tile.hip", "paper_2212_14201_amd/csrc/tile.hpp"],
+}
+
+
+def stored_traffic(kernel, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, scaled by
+    the copy-kernel factor; None when absent or when the kernel source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(kernel)
+    if not rec or rec.get("src_sha") != src_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n, x, gates, budget_s, plain_bytes_fn):
+    """The FP64 oracle on the host cores: a strided sample of the workload's
+    gates (every 25th, in order) applied to the 30-qubit state, until the
+    sample or the time budget runs out."""
+    import numpy as np
+    import oracle
+    sample = gates[::25]
+    psi = oracle.basis_state(n, x)
+    done = []
+    t0 = time.perf_counter()
+    for g in sample:
+        oracle.apply_matrix(psi, n, oracle.gate_matrix(g), g.targets, g.controls)
+        done.append(g)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    del psi
+    return {"value": len(done) / dt, "unit": "gates/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{len(done)} gates (every 25th gate of the workload, in order) applied "
+                      f"in complex128 to the {n}-qubit state by the FP64 oracle in {dt:.1f} s",
+            "effective_GBs": plain_bytes_fn(done, n, 16) / dt / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--k-max", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=13, help="tile qubits per pass (0: one block per pass)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the complex128 comparison path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the state would shard by its top qubits across GPUs; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2212_14201_amd import qvm, profiling
+    from workloads import config_circuit, uniform_stream
+
+    cfg = config_circuit("qft30")
+    n, x, gates = cfg["n"], cfg["init"], cfg["gates"]
+    ga = qvm.GateArray(gates)
+    uniforms = uniform_stream(3002, 1024)
+    zz_x = np.zeros(n - 1, dtype=np.uint64)
+    zz_z = np.array([(1 << q) | (1 << (q + 1)) for q in range(n - 1)], dtype=np.uint64)
+    fused = qvm.StateVector(n, "c64", init=None)
+    plain = None if args.no_plain else qvm.StateVector(n, "c128", init=None)
+    torch.cuda.synchronize()
+
+    def step():
+        r = {}
+        t0 = time.perf_counter()
+        plan = qvm.Plan(ga, n, "c64", k_max=args.k_max, tile_qubits=args.tile)
+        t1 = time.perf_counter()
+        fused.init_basis(x)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run(fused)
+        e1.record()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r["plan_s"] = t1 - t0
+        r["fused_run_s"] = e0.elapsed_time(e1) / 1e3
+        r["fused_e2e_s"] = t2 - t0
+        r["stats"] = plan.stats()
+        t3 = time.perf_counter()
+        r["z"] = fused.expect_z_all()
+        r["zz"], _ = fused.expect_pauli(zz_x, zz_z)
+        r["marg"] = fused.probabilities(list(range(8)))
+        r["samples"] = fused.sample(uniforms)
+        r["norm_before"] = fused.renormalize()
+        r["readout_s"] = time.perf_counter() - t3
+        if plain is not None:
+            plain.init_basis(x)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e3 = torch.cuda.Event(enable_timing=True)
+            e2.record()
+            plain.run(ga)
+            e3.record()
+            r["z128"] = plain.expect_z_all()
+            r["plain_run_s"] = e2.elapsed_time(e3) / 1e3
+        return r
+
+    for _ in range(args.warmup):
+        step()
+    profiling.begin(fused)
+    if plain is not None:
+        profiling.begin(plain)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kstats = {"c64:" + k: v for k, v in profiling.end(fused).items()}
+    if plain is not None:
+        kstats.update({"c128:" + k: v for k, v in profiling.end(plain).items()})
+
+    G = len(gates)
+    fused_run = float(np.mean([r["fused_run_s"] for r in recs]))
+    fused_e2e = float(np.mean([r["fused_e2e_s"] for r in recs]))
+    st = recs[-1]["stats"]
+    N = 1 << n
+    fused_info = {
+        "run_ms": fused_run * 1e3, "plan_ms": float(np.mean([r["plan_s"] for r in recs])) * 1e3,
+        "end_to_end_ms": fused_e2e * 1e3,
+        "readout_ms": float(np.mean([r["readout_s"] for r in recs])) * 1e3,
+        "gates_per_s": G / fused_run, "gates_per_s_end_to_end": G / fused_e2e,
+        "effective_GBs": plain_bytes(gates, n, 8) / fused_run / 1e9,
+        "pass_GBs": st["passes"] * 2.0 * N * 8 / fused_run / 1e9,
+        "passes": st["passes"], "blocks": st["blocks"], "blocks_by_k": st["blocks_by_k"],
+        "diag_ops": st["diag_ops"], "k_max": args.k_max, "tile_qubits": args.tile,
+        "norm_before_renormalize": float(recs[-1]["norm_before"]),
+    }
+    out = {"metric": METRIC, "value": G / fused_e2e, "unit": "gates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "qft30: QFT on a seeded basis state then 30 layers of random U3 + "
+                                  "CZ brick, 30 qubits, 1815 gates",
+                      "n_qubits": n, "gates": G, "fused_dtype": "complex64",
+                      "plain_dtype": "complex128", "planner": "greedy"},
+           "fused_c64": fused_info}
+    if plain is not None:
+        prun = float(np.mean([r["plain_run_s"] for r in recs]))
+        pbytes = plain_bytes(gates, n, 16)
+        out["plain_c128"] = {"run_ms": prun * 1e3, "gates_per_s": G / prun,
+                             "effective_GBs": pbytes / prun / 1e9,
+                             "frac_of_hbm_peak": pbytes / prun / 1e9 / HBM_PEAK_GBS}
+        out["speedup_fused_c64_vs_plain_c128"] = prun / fused_run
+        z64, z128 = recs[-1]["z"], recs[-1]["z128"]
+        out["fused_c64_max_abs_z_error_vs_c128"] = float(np.max(np.abs(z64 - z128)))
+    # roofline of the kernel class with the largest share of the timed region
+    dom_name, dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
+    per_launch_s = dom["total_ms"] / dom["launches"] / 1e3
+    bpl = dom["bytes"] / dom["launches"]
+    fpl = dom["flops"] / dom["launches"]
+    prec = "f32" if dom_name.startswith("c64") else "f64"
+    if fpl / max(bpl, 1.0) > MFMA_PEAK[prec] / (HBM_PEAK_GBS * 1e9):
+        ach = fpl / per_launch_s / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": MFMA_PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                "frac": ach / (MFMA_PEAK[prec] / 1e12)}
+    else:
+        ach = bpl / per_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS}
+    roof["kernel"] = dom_name
+    roof["launches_timed"] = dom["launches"]
+    roof["avg_launch_ms"] = per_launch_s * 1e3
+    roof["algorithmic_bytes_per_launch"] = bpl
+    roof["traffic"] = stored_traffic(dom_name.split(":")[1], bpl)
+    out["roofline"] = roof
+    out["kernels"] = {k: {"launches": v["launches"], "total_ms": v["total_ms"],
+                          "GBs": v["bytes"] / (v["total_ms"] / 1e3) / 1e9 if v["total_ms"] else None,
+                          "TFLOPs": v["flops"] / (v["total_ms"] / 1e3) / 1e12 if v["total_ms"] else None}
+                      for k, v in kstats.items()}
+    del fused, plain
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, x, gates, args.cpu_seconds, plain_bytes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -270,6 +270,29 @@ qvm_status qvm_plan_image(const qvm_plan* plan, void* out, size_t cap, size_t* b
 
 qvm_status qvm_plan_destroy(qvm_plan* plan);
 
+/* --------------------------------------------------------------- timing */
+
+/* Per-launch kernel timing for one state: between qvm_profile_begin and
+ * qvm_profile_end every kernel the library launches for the state is
+ * bracketed by two HIP events recorded on the state's stream.  The
+ * durations are aggregated per kernel class together with the algorithmic
+ * bytes (amplitudes the launch must read and write, times their size) and
+ * flops (complex multiply-adds of dense and fused matrices, 8 flops each).
+ * Used to report achieved bandwidth and throughput against the roofline. */
+typedef struct qvm_kernel_stat {
+    char name[24];           /* dense1..dense3, diag, phase, swappair, tile, basis */
+    int64_t launches;
+    double total_ms;
+    double bytes;
+    double flops;
+} qvm_kernel_stat;
+
+qvm_status qvm_profile_begin(qvm_sv* sv);
+
+/* Synchronises the stream, writes up to max aggregated records into out
+ * (nullable) and their number into *count, and stops recording. */
+qvm_status qvm_profile_end(qvm_sv* sv, qvm_kernel_stat* out, int32_t max, int32_t* count);
+
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* qvm_last_error(void);
 

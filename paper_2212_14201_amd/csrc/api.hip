@@ -314,6 +314,8 @@ qvm_status qvm_sv_create(int n, qvm_dtype dt, void* amps, void* work, size_t wor
 }
 
 qvm_status qvm_sv_destroy(qvm_sv* sv) {
+    if (sv)
+        for (hipEvent_t e : sv->prof.events) (void)hipEventDestroy(e);
     delete sv;
     return QVM_OK;
 }

@@ -154,9 +154,12 @@ static qvm_status launch_dense_k(qvm_sv* sv, const LOp& op) {
         a.m[2 * i] = (R)op.m[i].real();
         a.m[2 * i + 1] = (R)op.m[i].imag();
     }
+    const double touched = (double)a.items * (1 << K);
+    const int tok = prof_begin(sv);
     hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
                        (T*)sv->amps, a);
     QVM_LAUNCH_CHECK(sv);
+    prof_end(sv, tok, PK_DENSE1 + K - 1, 2.0 * touched * sizeof(T), touched * 8.0 * (1 << K));
     return QVM_OK;
 }
 
@@ -167,10 +170,12 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
         case OP_PHASE: {
             if (op.phase == cd(1.0, 0.0)) return QVM_OK;   // identity
             uint64_t items = 1ull << (sv->n - popc(op.cond_mask));
+            const int tok = prof_begin(sv);
             hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
                                (T*)sv->amps, items, op.cond_mask, op.cond_val,
                                (R)op.phase.real(), (R)op.phase.imag());
             QVM_LAUNCH_CHECK(sv);
+            prof_end(sv, tok, PK_PHASE, 2.0 * items * sizeof(T), 6.0 * items);
             return QVM_OK;
         }
         case OP_DIAG: {
@@ -184,17 +189,21 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
                 a.d[2 * j] = (R)op.m[j].real();
                 a.d[2 * j + 1] = (R)op.m[j].imag();
             }
+            const int tok = prof_begin(sv);
             hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
                                (T*)sv->amps, a);
             QVM_LAUNCH_CHECK(sv);
+            prof_end(sv, tok, PK_DIAG, 2.0 * a.items * sizeof(T), 6.0 * a.items);
             return QVM_OK;
         }
         case OP_SWAPPAIR: {
             uint64_t fixed = op.cond_mask | op.hbit;
             uint64_t items = 1ull << (sv->n - popc(fixed));
+            const int tok = prof_begin(sv);
             hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
                                (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
             QVM_LAUNCH_CHECK(sv);
+            prof_end(sv, tok, PK_SWAP, 4.0 * items * sizeof(T), 0.0);
             return QVM_OK;
         }
         case OP_DENSE:
@@ -214,6 +223,7 @@ qvm_status launch_op(qvm_sv* sv, const LOp& op) {
 
 qvm_status launch_init_basis(qvm_sv* sv, uint64_t idx) {
     uint64_t N = 1ull << sv->n;
+    const int tok = prof_begin(sv);
     if (sv->dt == QVM_C64)
         hipLaunchKernelGGL((k_basis<float>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
                            (float2*)sv->amps, N, idx);
@@ -221,6 +231,7 @@ qvm_status launch_init_basis(qvm_sv* sv, uint64_t idx) {
         hipLaunchKernelGGL((k_basis<double>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
                            (double2*)sv->amps, N, idx);
     QVM_LAUNCH_CHECK(sv);
+    prof_end(sv, tok, PK_BASIS, (double)N * (sv->dt == QVM_C64 ? 8 : 16), 0.0);
     return QVM_OK;
 }
 

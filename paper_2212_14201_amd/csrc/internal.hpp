@@ -33,6 +33,20 @@ WorkLayout work_layout(int n, qvm_dtype dt);
 constexpr int kRedBlocks = 2048;      // fixed grid of reduction kernels
 constexpr int kRedSlots = 64;         // doubles per block in the partials table
 
+// Per-launch timing with HIP events (enabled by qvm_profile_begin).
+enum ProfKind { PK_DENSE1 = 0, PK_DENSE2, PK_DENSE3, PK_DIAG, PK_PHASE, PK_SWAP, PK_TILE,
+                PK_BASIS, PK_COUNT };
+struct ProfRec {
+    int kind;
+    int ev;                           // index of the start event; end = ev + 1
+    double bytes, flops;              // algorithmic bytes and flops of the launch
+};
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> events;   // pool, grows on demand
+    std::vector<ProfRec> recs;
+};
+
 }  // namespace qvm
 
 struct qvm_sv {
@@ -45,6 +59,7 @@ struct qvm_sv {
     int perm[QVM_MAX_QUBITS];         // logical -> physical bit
     bool failed;
     qvm::WorkLayout lay;
+    qvm::Prof prof;
 };
 
 namespace qvm {
@@ -57,6 +72,10 @@ qvm_status device_fail(qvm_sv* sv, hipError_t e, const char* where);
         if (_e != hipSuccess) return ::qvm::device_fail(sv, _e, #expr); \
     } while (0)
 #define QVM_LAUNCH_CHECK(sv) QVM_HIP(sv, hipGetLastError())
+
+// Bracket a launch: prof_begin returns a token (-1 when profiling is off).
+int prof_begin(qvm_sv* sv);
+void prof_end(qvm_sv* sv, int token, int kind, double bytes, double flops);
 
 // Logical mask -> physical mask through the handle's layout.
 uint64_t phys_mask(const qvm_sv* sv, uint64_t logical_mask);

@@ -33,7 +33,7 @@
 
 namespace qvm {
 
-qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev);
+qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, double flops);
 
 namespace {
 
@@ -69,6 +69,7 @@ struct qvm_plan {
     int tile_qubits;
     std::vector<char> blob;                 // device image
     std::vector<qvm::PassDesc> passes;
+    std::vector<double> pass_flops;         // MFMA flops of each pass over the whole state
     std::vector<int> final_perm;            // logical qubit -> physical bit after the plan
     std::vector<uint32_t> block_of_gate;    // pass-ordered block id per input gate (-1: diag op)
     std::vector<int32_t> exec_pos;          // rank of each input gate in execution order (-1: relabel)
@@ -630,6 +631,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 }
             }
         }
+        double fl = 0;
+        for (const TOp& o : ops)
+            if (o.type == TOP_BLOCK) fl += 8.0 * (double)(1 << o.k) * (double)(1ull << n);
+        P->pass_flops.push_back(fl);
         P->passes.push_back(pd);
     }
     P->final_perm.resize(n);
@@ -646,8 +651,8 @@ qvm_status run_plan(qvm_sv* sv, const qvm_plan* P) {
     char* dblob = sv->work + sv->lay.plan_off;
     if (!P->blob.empty())
         QVM_HIP(sv, hipMemcpyAsync(dblob, P->blob.data(), P->blob.size(), hipMemcpyHostToDevice, sv->stream));
-    for (const PassDesc& pd : P->passes) {
-        qvm_status st = launch_tile_pass(sv, pd, dblob);
+    for (size_t i = 0; i < P->passes.size(); ++i) {
+        qvm_status st = launch_tile_pass(sv, P->passes[i], dblob, P->pass_flops[i]);
         if (st) return st;
     }
     for (int q = 0; q < sv->n; ++q) sv->perm[q] = P->final_perm[q];

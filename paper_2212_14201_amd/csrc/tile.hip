@@ -335,7 +335,8 @@ size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
 }
 
 template <typename R>
-static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, size_t lds) {
+static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, size_t lds,
+                                double flops) {
     static bool attr_set[16] = {};
     const unsigned grid = 1u << (sv->n - pd.L);
     const void* fn = nullptr;
@@ -355,15 +356,17 @@ static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob
     }
     R* amps = (R*)sv->amps;
     void* args[] = {(void*)&amps, (void*)&pd, (void*)&blob_dev};
+    const int tok = prof_begin(sv);
     QVM_HIP(sv, hipLaunchKernel(fn, dim3(grid), dim3(NT), args, lds, sv->stream));
+    prof_end(sv, tok, PK_TILE, 2.0 * (double)(1ull << sv->n) * 2 * sizeof(R), flops);
     return QVM_OK;
 }
 
-qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev) {
+qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, double flops) {
     const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax);
     if (lds > kTileLdsMax) return fail(QVM_EUNSUPPORTED, "pass needs more LDS than a workgroup has");
-    return sv->dt == QVM_C64 ? launch_tile_t<float>(sv, pd, blob_dev, lds)
-                             : launch_tile_t<double>(sv, pd, blob_dev, lds);
+    return sv->dt == QVM_C64 ? launch_tile_t<float>(sv, pd, blob_dev, lds, flops)
+                             : launch_tile_t<double>(sv, pd, blob_dev, lds, flops);
 }
 
 }  // namespace qvm

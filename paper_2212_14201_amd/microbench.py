@@ -1,0 +1,55 @@
+"""Launch one kernel class a few times at a given size, for counter runs.
+
+Used under ``rocprofv3 --pmc`` to read HBM traffic (FETCH_SIZE, WRITE_SIZE)
+of a single kernel class, and with ``--kernel copy`` to read the same
+counters for a plain device copy of known size (the scale factor).
+
+    python -m paper_2212_14201_amd.microbench --kernel dense1 --n 30 --dtype c128
+    python -m paper_2212_14201_amd.microbench --kernel tile --n 30 --dtype c64
+    python -m paper_2212_14201_amd.microbench --kernel copy --n 30 --dtype c128
+"""
+import argparse
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kernel", choices=["dense1", "tile", "copy"], required=True)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--dtype", default="c128")
+    ap.add_argument("--launches", type=int, default=3)
+    a = ap.parse_args()
+    import torch
+    from paper_2212_14201_amd import qvm
+    from workloads import Gate, config_circuit
+
+    if a.kernel == "copy":
+        real = torch.float32 if a.dtype == "c64" else torch.float64
+        src = torch.zeros(2 << a.n, dtype=real, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(a.launches):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy of {src.numel() * src.element_size()} bytes x {a.launches}", flush=True)
+        return
+    sv = qvm.StateVector(a.n, a.dtype, init=0)
+    if a.kernel == "dense1":
+        g = Gate("u3", (a.n // 3,), (), (0.3, 0.2, 0.1))
+        for _ in range(a.launches):
+            sv.apply(g)
+    else:
+        cfg = config_circuit("qft30") if a.n == 30 else None
+        gates = cfg["gates"] if cfg else [Gate("h", (q,)) for q in range(a.n)]
+        plan = qvm.Plan(gates, a.n, a.dtype, k_max=4, tile_qubits=13 if a.dtype == "c64" else 12)
+        for _ in range(a.launches):
+            sv.init_basis(0)
+            plan.run(sv)
+    torch.cuda.synchronize()
+    print(f"{a.kernel} n={a.n} {a.dtype} x {a.launches}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
