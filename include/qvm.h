@@ -270,6 +270,35 @@ qvm_status qvm_plan_image(const qvm_plan* plan, void* out, size_t cap, size_t* b
 
 qvm_status qvm_plan_destroy(qvm_plan* plan);
 
+/* ------------------------------------------------------------- gradients */
+
+/* Bytes of device workspace qvm_adjoint_expect_grad needs. */
+size_t qvm_adjoint_workspace_bytes(int n_qubits, int batch, size_t n_gates);
+
+/* Expectation f_b = <psi(theta_b)|H|psi(theta_b)> of H = sum_t coeff[t] P_t
+ * (Pauli strings in symplectic form, as in qvm_expect_pauli) for a batch of
+ * parameter vectors, and its gradient by the adjoint reverse sweep
+ * (Jones & Gacon, arXiv:2009.02823) — the paper's variational circuits
+ * ("Variational quantum circuit": parameters updated, circuit re-run, qop
+ * expectation) differentiated without finite differences.
+ * The circuit starts from |0..0>; every gate has one target (k = 1) and any
+ * controls.  param_index[i] = -1 for a fixed gate, else the index of the
+ * gate's angle in a parameter row; such gates must be RX, RY or RZ (their
+ * stored params are ignored).  params_host is [batch][n_params] row-major.
+ * psi_dev and lam_dev each hold batch x 2^n amplitudes of dt (caller-owned,
+ * distinct); work_dev at least qvm_adjoint_workspace_bytes.  Outputs on the
+ * host: f_out[batch]; grad_out[batch][n_params] (NULL: expectation only).
+ * All batch elements run together, one launch per gate; sums in double
+ * precision.  Synchronous on hip_stream. */
+qvm_status qvm_adjoint_expect_grad(int n_qubits, qvm_dtype dt, int batch,
+                                   const qvm_gate* gates, size_t n_gates,
+                                   const int32_t* param_index, int n_params,
+                                   const double* params_host, size_t n_terms,
+                                   const uint64_t* x_mask, const uint64_t* z_mask,
+                                   const double* coeff, void* psi_dev, void* lam_dev,
+                                   void* work_dev, size_t work_bytes, void* hip_stream,
+                                   double* f_out, double* grad_out);
+
 /* --------------------------------------------------------------- timing */
 
 /* Per-launch kernel timing for one state: between qvm_profile_begin and
