@@ -260,6 +260,20 @@ qvm_status qvm_plan_final_layout(const qvm_plan* plan, int32_t* perm_out);
  * plan's final layout; readouts account for it.  Asynchronous. */
 qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* plan);
 
+/* Features of every pass for the learned cost model, QVM_PASS_FEATURES
+ * floats per pass in execution order: 0 n, 1 dtype (0 complex64, 1
+ * complex128), 2 tile qubits L, 3..6 blocks of k = 3, 4, 5, 6 (after
+ * padding), 7 sum of 2^k over blocks, 8 diagonal runs, 9 diagonal phase
+ * terms, 10 gates applied, 11 remap (0/1), 12 tile bits at physical
+ * positions >= 20, 13 mean, 14 min, 15 max physical position of block
+ * qubits, 16 block qubits on the always-tile low bits, 17 qubits spanned by
+ * the blocks' gates (before padding), 18 log2 state bytes, 19 log2 tile
+ * count.  out needs cap >= n_passes * QVM_PASS_FEATURES floats (NULL: only
+ * *n_passes is set). */
+#define QVM_PASS_FEATURES 20
+qvm_status qvm_plan_pass_features(const qvm_plan* plan, float* out, size_t cap,
+                                  int32_t* n_passes);
+
 /* The plan's device image as uploaded by qvm_run_plan (for inspection and
  * emulation): *bytes receives its size; when out is not NULL, cap >= that
  * size bytes are copied to it.  *pass_table receives the byte offset of the
@@ -299,6 +313,28 @@ qvm_status qvm_adjoint_expect_grad(int n_qubits, qvm_dtype dt, int batch,
                                    void* work_dev, size_t work_bytes, void* hip_stream,
                                    double* f_out, double* grad_out);
 
+/* ------------------------------------------------------------ cost model */
+
+/* A three-layer perceptron (d features -> H -> H -> 1, ReLU) that predicts
+ * the log time of a fused pass from its features; the learned fusion planner
+ * uses it to choose among candidate plans.  FP32, device pointers, all
+ * asynchronous on `stream`.  Parameters are packed [W1 (d x H), b1 (H),
+ * W2 (H x H), b2 (H), W3 (H x 1), b3 (1)], row-major, count from
+ * qvm_mlp_param_count.  X is [B][d] row-major.
+ * forward:  act receives Z1, H1, Z2, H2 (4 B H floats), y receives B outputs.
+ * backward: loss L = (1/B) sum (y - t)^2; grads (packed like params) get dL;
+ *           work holds 2 B H + B floats; loss_dev (nullable) receives L.
+ * adam:     one Adam step (Kingma & Ba) with bias correction; step >= 1. */
+size_t qvm_mlp_param_count(int d, int hidden);
+qvm_status qvm_mlp_forward(int batch, int d, int hidden, const float* X, const float* params,
+                           float* act, float* y, void* stream);
+qvm_status qvm_mlp_backward(int batch, int d, int hidden, const float* X, const float* t,
+                            const float* params, const float* act, const float* y, float* grads,
+                            float* work, float* loss_dev, void* stream);
+qvm_status qvm_mlp_adam_step(size_t n_params, float* params, const float* grads, float* m,
+                             float* v, int step, float lr, float beta1, float beta2, float eps,
+                             void* stream);
+
 /* --------------------------------------------------------------- timing */
 
 /* Per-launch kernel timing for one state: between qvm_profile_begin and
@@ -319,8 +355,16 @@ typedef struct qvm_kernel_stat {
 qvm_status qvm_profile_begin(qvm_sv* sv);
 
 /* Synchronises the stream, writes up to max aggregated records into out
- * (nullable) and their number into *count, and stops recording. */
+ * (nullable) and their number into *count, and stops recording.  The
+ * individual launches stay readable with qvm_profile_launches until the next
+ * qvm_profile_begin. */
 qvm_status qvm_profile_end(qvm_sv* sv, qvm_kernel_stat* out, int32_t max, int32_t* count);
+
+/* Per-launch durations (ms) and kernel classes (index into the class list
+ * above: 0 dense1 .. 7 basis) of the last profiled interval, in launch
+ * order; up to max entries, *count = the number recorded. */
+qvm_status qvm_profile_launches(const qvm_sv* sv, double* ms, int32_t* kind, int32_t max,
+                                int32_t* count);
 
 /* Thread-local message for the last non-OK status returned on this thread. */
 const char* qvm_last_error(void);

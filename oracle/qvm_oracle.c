@@ -154,7 +154,7 @@ void orc_apply(double* psi, int n, const double* u, int k, const int* t,
     uint64_t tmask = 0;
     for (int r = 0; r < k; ++r) tmask |= (uint64_t)1 << t[r];
     int64_t NN = (int64_t)N;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (NN >= (1 << 14))
     for (int64_t bb = 0; bb < NN; ++bb) {
         uint64_t b = (uint64_t)bb;
         if (b & tmask) continue;
@@ -197,7 +197,7 @@ void orc_run(double* psi, int n, int64_t ngates, const double* mats,
 /* ------------------------------------------------------------------ */
 void orc_probabilities(const double* psi, int n, double* p) {
     int64_t N = (int64_t)1 << n;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int64_t i = 0; i < N; ++i)
         p[i] = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
 }
@@ -220,7 +220,7 @@ void orc_marginal(const double* psi, int n, int m, const int* q, double* out) {
 double orc_norm2(const double* psi, int n) {
     int64_t N = (int64_t)1 << n;
     double part[ORC_NCHUNK];
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int c = 0; c < ORC_NCHUNK; ++c) {
         int64_t lo = N * c / ORC_NCHUNK, hi = N * (c + 1) / ORC_NCHUNK;
         orc_acc a = {0, 0};
@@ -246,7 +246,7 @@ double orc_expect_pauli(const double* psi, int n, uint64_t x, uint64_t z,
                         double* im_out) {
     int64_t N = (int64_t)1 << n;
     double pre[ORC_NCHUNK], pim[ORC_NCHUNK];
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int c = 0; c < ORC_NCHUNK; ++c) {
         int64_t lo = N * c / ORC_NCHUNK, hi = N * (c + 1) / ORC_NCHUNK;
         orc_acc ar = {0, 0}, ai = {0, 0};
@@ -283,7 +283,7 @@ void orc_apply_pauli(const double* psi, int n, uint64_t x, uint64_t z,
                      double coeff, double* out, int accumulate) {
     int64_t N = (int64_t)1 << n;
     int c = popc64(x & z) & 3;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int64_t i = 0; i < N; ++i) {
         uint64_t j = (uint64_t)i ^ x;
         double vr = psi[2 * j], vi = psi[2 * j + 1];
@@ -372,7 +372,7 @@ static double inner_im(const double* a, const double* b, int n) {
     /* Im sum conj(a_i) b_i, chunked compensated */
     int64_t N = (int64_t)1 << n;
     double part[ORC_NCHUNK];
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int c = 0; c < ORC_NCHUNK; ++c) {
         int64_t lo = N * c / ORC_NCHUNK, hi = N * (c + 1) / ORC_NCHUNK;
         orc_acc s = {0, 0};
@@ -388,7 +388,7 @@ static double inner_im(const double* a, const double* b, int n) {
 static double inner_re(const double* a, const double* b, int n) {
     int64_t N = (int64_t)1 << n;
     double part[ORC_NCHUNK];
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= (1 << 14))
     for (int c = 0; c < ORC_NCHUNK; ++c) {
         int64_t lo = N * c / ORC_NCHUNK, hi = N * (c + 1) / ORC_NCHUNK;
         orc_acc s = {0, 0};

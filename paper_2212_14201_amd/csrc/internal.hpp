@@ -45,6 +45,8 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> events;   // pool, grows on demand
     std::vector<ProfRec> recs;
+    std::vector<double> last_ms;      // per-launch durations of the last interval
+    std::vector<int> last_kind;
 };
 
 }  // namespace qvm

@@ -70,6 +70,7 @@ struct qvm_plan {
     std::vector<char> blob;                 // device image
     std::vector<qvm::PassDesc> passes;
     std::vector<double> pass_flops;         // MFMA flops of each pass over the whole state
+    std::vector<float> pass_features;       // QVM_PASS_FEATURES per pass
     std::vector<int> final_perm;            // logical qubit -> physical bit after the plan
     std::vector<uint32_t> block_of_gate;    // pass-ordered block id per input gate (-1: diag op)
     std::vector<int32_t> exec_pos;          // rank of each input gate in execution order (-1: relabel)
@@ -635,6 +636,53 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         for (const TOp& o : ops)
             if (o.type == TOP_BLOCK) fl += 8.0 * (double)(1 << o.k) * (double)(1ull << n);
         P->pass_flops.push_back(fl);
+        {
+            // features of the pass for the cost model (layout in qvm.h)
+            float f[QVM_PASS_FEATURES] = {};
+            f[0] = (float)n;
+            f[1] = dt == QVM_C64 ? 0.f : 1.f;
+            f[2] = (float)L;
+            int nb = 0, nlow = 0, ktrue = 0, ngates = 0, nruns = 0, nterms = 0;
+            double pos_sum = 0, pos_min = 64, pos_max = -1, work = 0;
+            for (const TOp& o : ops) {
+                if (o.type == TOP_BLOCK) {
+                    f[3 + (o.k - 3)] += 1.f;
+                    work += (double)(1 << o.k);
+                    ++nb;
+                    for (int r = 0; r < o.k; ++r) {
+                        const double ph = phys[o.lb[r]];
+                        pos_sum += ph;
+                        pos_min = std::min(pos_min, ph);
+                        pos_max = std::max(pos_max, ph);
+                        if (ph < c) ++nlow;
+                    }
+                } else {
+                    ++nruns;
+                    nterms += o.k;
+                }
+            }
+            for (auto& u : pp.units) {
+                ngates += (int)u.gates.size();
+                if (u.block) ktrue += (int)u.qubits.size();
+            }
+            int high = 0;
+            for (int i = 0; i < L; ++i)
+                if (phys[i] >= 20) ++high;
+            f[7] = (float)work;
+            f[8] = (float)nruns;
+            f[9] = (float)nterms;
+            f[10] = (float)ngates;
+            f[11] = pd.remap ? 1.f : 0.f;
+            f[12] = (float)high;
+            f[13] = nb ? (float)(pos_sum / std::max(1, [&] { int t = 0; for (const TOp& o : ops) if (o.type == TOP_BLOCK) t += o.k; return t; }())) : 0.f;
+            f[14] = nb ? (float)pos_min : (float)n;
+            f[15] = nb ? (float)pos_max : 0.f;
+            f[16] = (float)nlow;
+            f[17] = (float)ktrue;
+            f[18] = (float)(n + (dt == QVM_C64 ? 3 : 4));     // log2 of state bytes
+            f[19] = (float)(n - L);                           // log2 of the tile count
+            P->pass_features.insert(P->pass_features.end(), f, f + QVM_PASS_FEATURES);
+        }
         P->passes.push_back(pd);
     }
     P->final_perm.resize(n);
@@ -674,6 +722,16 @@ qvm_status qvm_plan_from_partition(const qvm_gate* gates, size_t n_gates, const 
                                    int n_qubits, int k_max, qvm_dtype dt, qvm_plan** out) {
     if (n_gates && !block_of_gate) return fail(QVM_EARG, "NULL partition");
     return build_plan(gates, n_gates, n_qubits, dt, k_max, 0, block_of_gate, out);
+}
+
+qvm_status qvm_plan_pass_features(const qvm_plan* p, float* out, size_t cap, int32_t* n_passes) {
+    if (!p) return fail(QVM_EARG, "NULL plan");
+    if (n_passes) *n_passes = (int32_t)p->passes.size();
+    if (out) {
+        if (cap < p->pass_features.size()) return fail(QVM_ENOMEM, "feature buffer too small");
+        memcpy(out, p->pass_features.data(), p->pass_features.size() * sizeof(float));
+    }
+    return QVM_OK;
 }
 
 qvm_status qvm_plan_image(const qvm_plan* p, void* out, size_t cap, size_t* bytes,

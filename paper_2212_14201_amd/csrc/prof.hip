@@ -55,9 +55,13 @@ qvm_status qvm_profile_end(qvm_sv* sv, qvm_kernel_stat* out, int32_t max, int32_
     qvm_kernel_stat agg[PK_COUNT];
     memset(agg, 0, sizeof(agg));
     for (int k = 0; k < PK_COUNT; ++k) strncpy(agg[k].name, kProfNames[k], sizeof(agg[k].name) - 1);
+    P.last_ms.clear();
+    P.last_kind.clear();
     for (const ProfRec& r : P.recs) {
         float ms = 0;
         QVM_HIP(sv, hipEventElapsedTime(&ms, P.events[r.ev], P.events[r.ev + 1]));
+        P.last_ms.push_back(ms);
+        P.last_kind.push_back(r.kind);
         qvm_kernel_stat& a = agg[r.kind];
         a.launches += 1;
         a.total_ms += ms;
@@ -72,6 +76,19 @@ qvm_status qvm_profile_end(qvm_sv* sv, qvm_kernel_stat* out, int32_t max, int32_
             ++n;
         }
     if (count) *count = n;
+    return QVM_OK;
+}
+
+qvm_status qvm_profile_launches(const qvm_sv* sv, double* ms, int32_t* kind, int32_t max,
+                                int32_t* count) {
+    if (!sv) return fail(QVM_EARG, "NULL state handle");
+    const Prof& P = sv->prof;
+    const int32_t n = (int32_t)P.last_ms.size();
+    if (count) *count = n;
+    for (int32_t i = 0; i < n && i < max; ++i) {
+        if (ms) ms[i] = P.last_ms[i];
+        if (kind) kind[i] = P.last_kind[i];
+    }
     return QVM_OK;
 }
 

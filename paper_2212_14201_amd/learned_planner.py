@@ -1,0 +1,334 @@
+"""Learned fusion planner driven by the cost-model MLP.
+
+The greedy planner (``qvm_plan_greedy``) builds a plan for a given block
+width k_max and execution mode: one fused block per HBM pass (``tile = 0``)
+or tile passes that hold many blocks (``tile = L``).  Which choice is fastest
+depends on the circuit.  The learned planner builds every candidate plan on
+the host, predicts each pass's time with the MLP (features from
+``qvm_plan_pass_features``), and runs the candidate with the smallest
+predicted total.  The greedy planner with the classic setting (5-qubit
+blocks, one pass each) stays as the fallback and as the judge of plan
+quality; all candidates compute the same state up to rounding.
+
+The MLP is trained on pass timings the simulator measures itself (per-launch
+HIP events of the tile kernel), on seeded random circuits of 26-32 qubits with
+100-500 gates drawn from {H, T, RX, RZ, RZZ, CNOT, CZ, Toffoli}.
+
+    python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 2000 --out D.npz
+    python -m paper_2212_14201_amd.learned_planner train    --data D.npz --model M.npz
+    python -m paper_2212_14201_amd.learned_planner evaluate --model M.npz --first 100000 --count 200
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from . import qvm  # noqa: E402
+from .qvm import _i32p, _vp, check, lib  # noqa: E402
+
+NFEAT = 20
+CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
+              ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13), ("tile", 4, 12), ("tile", 3, 11)]
+GREEDY = ("block", 5, 0)       # fallback and judge: 5-qubit blocks, one pass each
+TILE_KIND = 6                  # kernel class index of the tile kernel in the profiler
+
+
+def _declare():
+    L = lib()
+    L.qvm_plan_pass_features.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t, _i32p]
+    L.qvm_plan_pass_features.restype = ctypes.c_int
+    L.qvm_profile_launches.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i32p, ctypes.c_int32, _i32p]
+    L.qvm_profile_launches.restype = ctypes.c_int
+    return L
+
+
+def cand_for_dtype(c, dtype):
+    mode, k, tile = c
+    if dtype == "c128" and tile > 12:
+        tile = 12
+    return mode, k, tile
+
+
+def build_plan(ga, n, dtype, cand):
+    mode, k, tile = cand_for_dtype(cand, dtype)
+    try:
+        return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile)
+    except qvm.QvmError:
+        return None        # e.g. a Toffoli does not fit 2-qubit blocks
+
+
+def plan_features(plan) -> np.ndarray:
+    L = _declare()
+    npass = ctypes.c_int32()
+    check(L.qvm_plan_pass_features(plan._h, None, 0, ctypes.byref(npass)))
+    out = np.zeros(npass.value * NFEAT, dtype=np.float32)
+    check(L.qvm_plan_pass_features(plan._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   out.size, ctypes.byref(npass)))
+    return out.reshape(npass.value, NFEAT)
+
+
+def tile_launch_ms(sv) -> np.ndarray:
+    L = _declare()
+    cnt = ctypes.c_int32()
+    check(L.qvm_profile_launches(sv.handle, None, None, 0, ctypes.byref(cnt)))
+    ms = np.zeros(cnt.value, dtype=np.float64)
+    kind = np.zeros(cnt.value, dtype=np.int32)
+    check(L.qvm_profile_launches(sv.handle, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 kind.ctypes.data_as(_i32p), cnt.value, ctypes.byref(cnt)))
+    return ms[kind == TILE_KIND]
+
+
+class StatePool:
+    """One state per (n, dtype) at a time (large states are freed first)."""
+
+    def __init__(self):
+        self.key, self.sv = None, None
+
+    def get(self, n, dtype):
+        import torch
+        if self.key != (n, dtype):
+            self.sv = None
+            torch.cuda.empty_cache()
+            self.sv = qvm.StateVector(n, dtype, init=0)
+            self.key = (n, dtype)
+        return self.sv
+
+
+def time_plan(sv, plan, x=0):
+    """Run a plan once with per-launch events; returns (total ms, pass ms)."""
+    from . import profiling
+    sv.init_basis(x)
+    profiling.begin(sv)
+    plan.run(sv)
+    profiling.end(sv)
+    ms = tile_launch_ms(sv)
+    return float(ms.sum()), ms
+
+
+def planner_circuit(seed, n_range=(26, 32), g_range=(100, 500)):
+    from workloads import random_planner_circuit
+    return random_planner_circuit(seed, n_range=n_range, g_range=g_range)
+
+
+# ------------------------------------------------------------------ collect
+def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_range=(100, 500)):
+    """Time one random candidate plan per circuit; save every pass's features
+    and measured milliseconds (npz: features, ms, seed, cand)."""
+    rng = np.random.Generator(np.random.PCG64(seed + first))
+    jobs = []
+    for s in range(first, first + count):
+        n, gates = planner_circuit(s, n_range, g_range)
+        jobs.append((n, s, gates, CANDIDATES[int(rng.integers(0, len(CANDIDATES)))]))
+    jobs.sort(key=lambda j: j[0])          # group by size to reuse the state buffer
+    pool = StatePool()
+    F, T, S, C = [], [], [], []
+    t0 = time.time()
+    for i, (n, s, gates, cand) in enumerate(jobs):
+        ga = qvm.GateArray(gates)
+        plan = build_plan(ga, n, dtype, cand)
+        if plan is None:
+            cand = ("block", 3, 0)
+            plan = build_plan(ga, n, dtype, cand)
+        sv = pool.get(n, dtype)
+        _, ms = time_plan(sv, plan)
+        feats = plan_features(plan)
+        F.append(feats)
+        T.append(ms)
+        S.append(np.full(len(ms), s, dtype=np.int32))
+        C.append(np.full(len(ms), CANDIDATES.index(cand), dtype=np.int32))
+        if (i + 1) % 100 == 0:
+            print(f"collect: {i + 1}/{len(jobs)} circuits, {sum(len(t) for t in T)} passes, "
+                  f"{time.time() - t0:.0f} s", flush=True)
+    F, T = np.concatenate(F), np.concatenate(T)
+    np.savez_compressed(out_path, features=F, ms=T, seed=np.concatenate(S), cand=np.concatenate(C))
+    return len(T)
+
+
+# -------------------------------------------------------------------- model
+class LearnedPlanner:
+    def __init__(self, net, mu, sd):
+        self.net, self.mu, self.sd = net, mu, sd
+
+    def predict_pass_ms(self, feats):
+        import torch
+        X = torch.tensor((feats - self.mu) / self.sd, dtype=torch.float32, device=self.net.device)
+        y = self.net.predict(X).cpu().numpy().astype(np.float64)
+        return np.exp(y)
+
+    def predict_plan_ms(self, plan):
+        return float(self.predict_pass_ms(plan_features(plan)).sum())
+
+    def choose(self, ga, n, dtype="c64"):
+        """Returns (candidate, plan, predicted ms) with the smallest prediction."""
+        best = None
+        for cand in CANDIDATES:
+            plan = build_plan(ga, n, dtype, cand)
+            if plan is None:
+                continue
+            p = self.predict_plan_ms(plan)
+            if best is None or p < best[2]:
+                best = (cand, plan, p)
+        return best
+
+    def save(self, path):
+        self.net.save(path, extra={"mu": self.mu, "sd": self.sd})
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        from .costmodel import CostMLP
+        net, z = CostMLP.load(path, device)
+        return cls(net, z["mu"], z["sd"])
+
+
+def load_rows(*paths):
+    F, T = [], []
+    for p in paths:
+        z = np.load(p, allow_pickle=False)
+        F.append(z["features"])
+        T.append(z["ms"])
+    return np.concatenate(F).astype(np.float32), np.concatenate(T).astype(np.float64)
+
+
+def train(F, T, epochs=60, batch=4096, lr=2e-3, hidden=128, seed=0, device="cuda", log=True):
+    """Fit log(ms) with the HIP MLP; returns (planner, history)."""
+    import torch
+    from workloads import mlp_init
+    from .costmodel import CostMLP
+    mu = F.mean(axis=0)
+    sd = F.std(axis=0) + 1e-6
+    X = torch.tensor((F - mu) / sd, dtype=torch.float32, device=device)
+    t = torch.tensor(np.log(T), dtype=torch.float32, device=device)
+    net = CostMLP(F.shape[1], hidden, init=mlp_init(F.shape[1], hidden, seed), device=device)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    hist = []
+    nb = max(1, (len(F) + batch - 1) // batch)
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(len(F)), device=device)
+        tot = 0.0
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            step_lr = lr * 0.5 * (1 + math.cos(math.pi * (ep * nb + b) / (epochs * nb)))
+            tot += float(net.train_step(X[idx].contiguous(), t[idx].contiguous(), step_lr).cpu())
+        hist.append(tot / nb)
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            print(f"train: epoch {ep} loss {hist[-1]:.4f}", flush=True)
+    return LearnedPlanner(net, mu, sd), hist
+
+
+# ----------------------------------------------------------------- evaluate
+def evaluate(planner, first, count, dtype="c64", all_cands=50, check_amplitudes=8, n_range=(26, 32),
+             g_range=(100, 500)):
+    """Held-out circuits: measured time of the learned choice against the
+    greedy planner (5-qubit blocks, one pass each), the best fixed setting
+    and, for the first `all_cands` circuits, every candidate."""
+    import torch
+    jobs = [(planner_circuit(s, n_range, g_range), s) for s in range(first, first + count)]
+    jobs.sort(key=lambda j: j[0][0])
+    pool = StatePool()
+    recs = []
+    t0 = time.time()
+    for i, ((n, gates), s) in enumerate(jobs):
+        ga = qvm.GateArray(gates)
+        cand, plan, pred = planner.choose(ga, n, dtype)
+        sv = pool.get(n, dtype)
+        learned_ms, _ = time_plan(sv, plan)
+        g_plan = build_plan(ga, n, dtype, GREEDY)
+        greedy_ms = time_plan(sv, g_plan)[0] if g_plan is not None else float("nan")
+        rec = {"seed": s, "n": n, "gates": len(gates), "choice": list(cand), "pred_ms": pred,
+               "learned_ms": learned_ms, "greedy_ms": greedy_ms}
+        if s - first < all_cands:
+            allm = {}
+            for c in CANDIDATES:
+                p = build_plan(ga, n, dtype, c)
+                if p is not None:
+                    allm["%s-%d-%d" % c] = time_plan(sv, p)[0]
+            rec["all_ms"] = allm
+        recs.append(rec)
+        if (i + 1) % 20 == 0:
+            print(f"evaluate: {i + 1}/{len(jobs)} circuits, {time.time() - t0:.0f} s", flush=True)
+    # amplitudes of the learned plan against the plain complex128 path
+    checks = []
+    if check_amplitudes:
+        pool = None
+        torch.cuda.empty_cache()
+        for (n, gates), s in sorted(jobs, key=lambda j: j[0][0])[:check_amplitudes]:
+            ga = qvm.GateArray(gates)
+            cand, plan, _ = planner.choose(ga, n, dtype)
+            fused = qvm.StateVector(n, dtype, init=0)
+            plan.run(fused)
+            plain = qvm.StateVector(n, "c128", init=0)
+            plain.run(ga)
+            idx = np.random.Generator(np.random.PCG64(s)).integers(0, 1 << n, 4096, dtype=np.uint64)
+            err = float(np.max(np.abs(fused.gather(idx) - plain.gather(idx))))
+            checks.append({"seed": s, "n": n, "choice": list(cand), "max_abs_err_vs_c128": err})
+            del fused, plain
+            torch.cuda.empty_cache()
+    return recs, checks
+
+
+def summarize(recs, checks):
+    sp = np.array([r["greedy_ms"] / r["learned_ms"] for r in recs if np.isfinite(r["greedy_ms"])])
+    out = {"circuits": len(recs), "median_speedup_vs_greedy": float(np.median(sp)),
+           "geomean_speedup_vs_greedy": float(np.exp(np.mean(np.log(sp)))),
+           "wins": int(np.sum(sp > 1.0)), "losses": int(np.sum(sp < 1.0)),
+           "learned_total_ms": float(sum(r["learned_ms"] for r in recs)),
+           "greedy_total_ms": float(sum(r["greedy_ms"] for r in recs))}
+    full = [r for r in recs if "all_ms" in r]
+    if full:
+        regret = [r["learned_ms"] / min(r["all_ms"].values()) for r in full]
+        fixed = {}
+        for r in full:
+            for k, v in r["all_ms"].items():
+                fixed.setdefault(k, []).append(v)
+        best_fixed = min(fixed, key=lambda k: sum(fixed[k]))
+        out.update({"all_candidates_measured": len(full),
+                    "learned_over_best_candidate_geomean": float(np.exp(np.mean(np.log(regret)))),
+                    "best_fixed_setting": best_fixed,
+                    "learned_vs_best_fixed_total": float(sum(fixed[best_fixed]) /
+                                                         sum(r["learned_ms"] for r in full))})
+    if checks:
+        out["max_abs_err_vs_c128"] = float(max(c["max_abs_err_vs_c128"] for c in checks))
+        out["amplitude_checks"] = len(checks)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["collect", "train", "evaluate"])
+    ap.add_argument("--first", type=int, default=0)
+    ap.add_argument("--count", type=int, default=2000)
+    ap.add_argument("--out", default="gpurun_out/planner_train.npz")
+    ap.add_argument("--data", nargs="+", default=["gpurun_out/planner_train.npz"])
+    ap.add_argument("--model", default="gpurun_out/costmodel.npz")
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--all-cands", type=int, default=50)
+    ap.add_argument("--report", default="gpurun_out/planner_eval.json")
+    a = ap.parse_args()
+    if a.cmd == "collect":
+        rows = collect(a.first, a.count, a.out)
+        print(f"collected {rows} pass timings", flush=True)
+    elif a.cmd == "train":
+        F, T = load_rows(*a.data)
+        planner, hist = train(F, T, epochs=a.epochs)
+        planner.save(a.model)
+        print(json.dumps({"rows": len(F), "final_loss": hist[-1]}), flush=True)
+    else:
+        planner = LearnedPlanner.load(a.model)
+        recs, checks = evaluate(planner, a.first, a.count, all_cands=a.all_cands)
+        summ = summarize(recs, checks)
+        with open(a.report, "w") as fh:
+            json.dump({"summary": summ, "records": recs, "checks": checks}, fh)
+        print(json.dumps(summ), flush=True)
+
+
+if __name__ == "__main__":
+    main()

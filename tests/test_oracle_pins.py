@@ -359,3 +359,42 @@ def test_plan_validator():
     assert not oracle.validate_plan(gates, [[0, 1, 2, 3]], 2)[0]        # too wide
     assert not oracle.validate_plan(gates, [[0, 1], [3]], 3)[0]         # gate missing
     assert not oracle.validate_plan(gates, [[3], [0, 1, 2]], 3)[0]      # z before h on qubit 2
+
+
+# ------------------------------------------------------------- cost-model MLP
+def test_mlp_backward_matches_central_differences():
+    from oracle import mlp
+    from workloads import mlp_init
+    rng = np.random.default_rng(0)
+    d, H, B = 5, 7, 9
+    params = mlp_init(d, H, 3)
+    for p in params:                      # nonzero biases so every term is exercised
+        p += 0.1 * rng.standard_normal(p.shape)
+    X = rng.standard_normal((B, d))
+    t = rng.standard_normal(B)
+    L0, grads = mlp.backward(params, X, t)
+    assert abs(L0 - mlp.loss(params, X, t)) < 1e-15
+    h = 1e-6
+    for pi, (p, g) in enumerate(zip(params, grads)):
+        flat, gflat = p.reshape(-1), g.reshape(-1)
+        for idx in range(0, flat.size, max(1, flat.size // 6)):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(params, X, t)
+            flat[idx] = old - h
+            lm = mlp.loss(params, X, t)
+            flat[idx] = old
+            assert abs((lp - lm) / (2 * h) - gflat[idx]) < 1e-7 * (1 + abs(gflat[idx])), (pi, idx)
+
+
+def test_adam_first_step_closed_form():
+    # with bias correction the first step moves each parameter by
+    # -lr * g / (|g| + eps)
+    from oracle import mlp
+    rng = np.random.default_rng(1)
+    p = [rng.standard_normal(6)]
+    g = [rng.standard_normal(6)]
+    m, v = [np.zeros(6)], [np.zeros(6)]
+    p0 = p[0].copy()
+    mlp.adam_step(p, g, m, v, 1, 0.01)
+    assert np.allclose(p[0], p0 - 0.01 * g[0] / (np.abs(g[0]) + 1e-8), atol=1e-15)

@@ -123,3 +123,17 @@ def test_plan_argument_errors():
         qvm.Plan(g, 20, "c64", k_max=5, tile_qubits=14)
     with pytest.raises(qvm.QvmError):
         qvm.Plan([Gate("h", (5,))], 3, "c64", k_max=3)
+
+
+def test_pass_features():
+    lp = pytest.importorskip("paper_2212_14201_amd.learned_planner")
+    cfg = config_circuit("qft30")
+    for k, tile in ((5, 0), (4, 13)):
+        plan = qvm.Plan(cfg["gates"], 30, "c64", k_max=k, tile_qubits=tile)
+        F = lp.plan_features(plan)
+        st = plan.stats()
+        assert F.shape == (st["passes"], lp.NFEAT)
+        assert np.all(F[:, 0] == 30) and np.all(F[:, 1] == 0) and np.all(F[:, 2] == 13)
+        assert F[:, 3:7].sum() == st["blocks"]
+        assert F[:, 10].sum() == len(cfg["gates"]) - 15        # swaps are relabelings
+        assert np.all(F[:, 18] == 33) and np.all(F[:, 19] == 17)
