@@ -90,19 +90,24 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
 // every k-step then reads one A value per row block and one B value per
 // column tile from LDS.  Fragment (rb, s), lane l holds
 // Mr[16 rb + l % 16][4 s + l / 16]; B feeds X rows 4 s + l / 16 of column
-// l % 16; the 16x16 result leaves rows 4 (l / 16) + r of column l % 16 in
-// lane l.  Each wave owns whole columns, so the in-place update needs no
-// barrier between its reads and writes.
+// l % 16; the 16x16 result leaves rows out_row(l / 16, r) of column l % 16
+// in register r of lane l.  Each wave owns whole columns, so the in-place
+// update needs no barrier between its reads and writes.
+//
+// Addressing: the LDS swizzle is linear over GF(2) and the column bits,
+// the lane's row bits and the k-step's row bits are disjoint, so every
+// address is a per-column constant XOR a per-lane constant XOR a
+// wave-uniform term.
 template <typename R, int K>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ ldsA, const TOp& op,
-                                        const char* __restrict__ blob, int L) {
+                                           const char* __restrict__ blob, int L) {
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
     constexpr int k = K == 16 ? 3 : K == 32 ? 4 : K == 64 ? 5 : 6;
     constexpr int CT = RB >= 4 ? 1 : 4 / RB;   // column tiles per wave iteration
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     {
         const R* __restrict__ frag = (const R*)(blob + op.data);
         for (int i = threadIdx.x; i < K * K; i += NT) ldsA[i] = frag[i];
@@ -114,18 +119,32 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
     uint32_t bmask = 0;
 #pragma unroll
     for (int r = 0; r < k; ++r) bmask |= 1u << lb[r];
+    auto scat = [&](int j) {                   // block row index -> tile bits
+        uint32_t e = 0;
+#pragma unroll
+        for (int q = 0; q < k; ++q)
+            if ((j >> q) & 1) e |= 1u << lb[q];
+        return e;
+    };
     const int ncol = 1 << (L - k);
     const int ntile = (ncol + 15) >> 4;
-    const int part = (lane >> 4) & 1;
-    const uint32_t hbit = (lane >> 5) ? (1u << lb[0]) : 0u;
+    const int g = lane >> 4;
+    const int part = g & 1;
+    // B operand: row 2 s + (l / 32): the lane's bit is row bit 0
+    const uint32_t swh = sw((lane >> 5) ? (1u << lb[0]) : 0u);
+    // epilogue: the lane's share of the output row index
+    const int jlane = TT<R>::out_row(g, 0) >> 1;
+    const int plane = TT<R>::out_row(g, 0) & 1;
+    const uint32_t swo = sw(scat(jlane));
+    const R* __restrict__ Arow = ldsA + lane;
     for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
-        uint32_t eb[CT];
+        uint32_t swe[CT];
         bool ok[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            int c = (t0 + ct) * 16 + (lane & 15);
+            const int c = (t0 + ct) * 16 + (lane & 15);
             ok[ct] = (t0 + ct) < ntile && c < ncol;
-            eb[ct] = ok[ct] ? dep32((uint32_t)c, bmask) : 0u;
+            swe[ct] = ok[ct] ? sw(dep32((uint32_t)c, bmask)) : 0u;
         }
         V4 acc[CT][RB];
 #pragma unroll
@@ -134,16 +153,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
             for (int rb = 0; rb < RB; ++rb) acc[ct][rb] = V4{0, 0, 0, 0};
 #pragma unroll 2
         for (int s = 0; s < KS; ++s) {
-            uint32_t js = hbit;
-#pragma unroll
-            for (int r = 1; r < k; ++r)
-                if ((s >> (r - 1)) & 1) js |= 1u << lb[r];
+            const uint32_t sj = sw(scat(2 * s)) ^ swh;
             R b[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds[2 * sw(eb[ct] | js) + part] : (R)0;
+            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds[2 * (swe[ct] ^ sj) + part] : (R)0;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                R av = ldsA[(rb * KS + s) * 64 + lane];
+                const R av = Arow[(rb * KS + s) * 64];
 #pragma unroll
                 for (int ct = 0; ct < CT; ++ct) acc[ct][rb] = mfma16(av, b[ct], acc[ct][rb]);
             }
@@ -153,16 +169,21 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
             if (!ok[ct]) continue;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
+                if constexpr (TT<R>::EP == 2) {
+                    // FP32: registers (0, 1) and (2, 3) are the (re, im) of
+                    // complex rows 8 rb + 2 g and 8 rb + 2 g + 1
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    // real output row held in register r of this lane
-                    const int i = 16 * rb + TT<R>::out_row(lane >> 4, r);
-                    const int jo = i >> 1;
-                    uint32_t e = eb[ct];
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const uint32_t sl = swe[ct] ^ swo ^ sw(scat(8 * rb + hh));
+                        *(float2*)(lds + 2 * sl) = make_float2(acc[ct][rb][2 * hh], acc[ct][rb][2 * hh + 1]);
+                    }
+                } else {
 #pragma unroll
-                    for (int q = 0; q < k; ++q)
-                        if ((jo >> q) & 1) e |= 1u << lb[q];
-                    lds[2 * sw(e) + (i & 1)] = acc[ct][rb][r];
+                    for (int r = 0; r < 4; ++r) {
+                        const int iu = 16 * rb + TT<R>::out_row(0, r);   // wave-uniform row bits
+                        const uint32_t sl = swe[ct] ^ swo ^ sw(scat(iu >> 1));
+                        lds[2 * sl + plane] = acc[ct][rb][r];
+                    }
                 }
             }
         }
@@ -181,7 +202,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
                                              int nsub, uint64_t base) {
     constexpr uint32_t nE = 1u << L;
     constexpr int NROW = nE >= NT ? (int)(nE / NT) : 1;   // elements per thread
-    constexpr int NPT = NROW < 16 ? NROW : 16;             // elements per sweep
+    constexpr int NPT = NROW < 8 ? NROW : 8;               // elements per sweep
     constexpr uint32_t LOWM = NT - 1;
     const uint32_t t = threadIdx.x;
     const bool live = t < nE;
@@ -203,6 +224,18 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
             const uint32_t lm = d.lmask, lv = d.lval;
             const bool hlo = (t & lm & LOWM) == (lv & LOWM);
             const uint32_t mhi = lm & ~LOWM, vhi = lv & ~LOWM;
+            if (d.neg) {
+                // factor -1 where the low bits match: a sign flip
+                const R sg = hlo ? (R)-1 : (R)1;
+#pragma unroll
+                for (int i = 0; i < NPT; ++i) {
+                    if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) {
+                        xr[i] *= sg;
+                        xi[i] *= sg;
+                    }
+                }
+                continue;
+            }
             // per-lane factor: the term's phase where the low bits match, else 1
             const R fr = hlo ? (R)d.pr : (R)1;
             const R fi = hlo ? (R)d.pi : (R)0;
@@ -228,7 +261,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
 
 // ---------------------------------------------------------------- kernel
 template <typename R, int L>
-__global__ __launch_bounds__(NT, 1) void k_tile(R* __restrict__ psi, PassDesc pd,
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
     extern __shared__ __align__(16) char smem[];
     R* lds = (R*)smem;
@@ -236,7 +269,7 @@ __global__ __launch_bounds__(NT, 1) void k_tile(R* __restrict__ psi, PassDesc pd
     constexpr int C = TT<R>::C < L ? TT<R>::C : L;          // low bits in every tile
     constexpr uint32_t NP = (1u << L) / EP;                  // 16-byte pieces per tile
     constexpr int NIT = NP >= NT ? (int)(NP / NT) : 1;       // pieces per thread
-    constexpr int BATCH = NIT < 8 ? NIT : 8;
+    constexpr int BATCH = NIT < 4 ? NIT : 4;
     constexpr uint32_t CM = (1u << C) - 1;
     using V16 = typename TT<R>::V16;
     R* ldsA = lds + (2u << L);               // block fragments follow the tile
