@@ -108,13 +108,65 @@ def cpu_baseline(n, x, gates, budget_s, plain_bytes_fn):
             "effective_GBs": plain_bytes_fn(done, n, 16) / dt / 1e9}
 
 
+def copy_bandwidth(torch, nbytes, reps=3):
+    """A plain device-to-device copy of nbytes (read + write), in GB/s: the
+    measured streaming ceiling beside the 8 TB/s peak."""
+    src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
+
+
+def adjoint_measure(torch, reps=2):
+    """Batched adjoint gradients: 20 qubits, complex64, 16 layers of RY, RZ
+    and a CNOT ladder (640 parameters, 944 gates), a 40-term Pauli sum, a
+    batch of 64 parameter vectors.  Algorithmic bytes per batch element:
+    start state (1 write), forward gates (read + write of what each
+    changes), the Pauli sum (read psi, write lambda), the value (read both)
+    and the reverse sweep (read + write of psi and lambda per gate)."""
+    import numpy as np
+    from paper_2212_14201_amd import adjoint
+    from workloads import SEEDS, hardware_efficient_ansatz, random_pauli_sum
+    n, layers, B = 20, 16, 64
+    gates, P = hardware_efficient_ansatz(n, layers)
+    xs, zs, cs, _ = random_pauli_sum(n, 40, SEEDS["pauli20"])
+    theta = np.random.Generator(np.random.PCG64(SEEDS["hea20"])).uniform(0, 2 * math.pi, (B, P))
+    prob = adjoint.AdjointProblem(n, gates, P, xs, zs, cs, B, "c64")
+    prob.run(theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        prob.run(theta)
+    dt = (time.perf_counter() - t0) / reps
+    S = float(1 << n) * 8
+    per = 5.0 * S
+    for g in gates:
+        per += 6.0 * S * 0.5 ** len(g.controls)
+    return {"workload": "20 qubits, complex64, 944 gates (640 RY/RZ + 304 CNOT), 40 Pauli terms, "
+                        "batch 64", "ms_per_batch": dt * 1e3, "gradients_per_s": B * P / dt,
+            "effective_GBs": per * B / dt / 1e9, "frac_of_hbm_peak": per * B / dt / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--planner", choices=["learned", "fixed"], default="learned",
+                    help="learned: the cost-model MLP picks among candidate plans (falls back to "
+                         "'fixed' when no trained model is present); fixed: --k-max/--tile")
     ap.add_argument("--k-max", type=int, default=4)
     ap.add_argument("--tile", type=int, default=13, help="tile qubits per pass (0: one block per pass)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 comparison path")
@@ -135,6 +187,10 @@ def main():
     uniforms = uniform_stream(3002, 1024)
     zz_x = np.zeros(n - 1, dtype=np.uint64)
     zz_z = np.array([(1 << q) | (1 << (q + 1)) for q in range(n - 1)], dtype=np.uint64)
+    planner = None
+    if args.planner == "learned":
+        from paper_2212_14201_amd import learned_planner
+        planner = learned_planner.load_default()
     fused = qvm.StateVector(n, "c64", init=None)
     plain = None if args.no_plain else qvm.StateVector(n, "c128", init=None)
     torch.cuda.synchronize()
@@ -142,7 +198,10 @@ def main():
     def step():
         r = {}
         t0 = time.perf_counter()
-        plan = qvm.Plan(ga, n, "c64", k_max=args.k_max, tile_qubits=args.tile)
+        if planner is not None:
+            r["choice"], plan, r["predicted_ms"] = planner.choose(ga, n, "c64")
+        else:
+            plan = qvm.Plan(ga, n, "c64", k_max=args.k_max, tile_qubits=args.tile)
         t1 = time.perf_counter()
         fused.init_basis(x)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -201,9 +260,20 @@ def main():
         "effective_GBs": plain_bytes(gates, n, 8) / fused_run / 1e9,
         "pass_GBs": st["passes"] * 2.0 * N * 8 / fused_run / 1e9,
         "passes": st["passes"], "blocks": st["blocks"], "blocks_by_k": st["blocks_by_k"],
-        "diag_ops": st["diag_ops"], "k_max": args.k_max, "tile_qubits": args.tile,
+        "diag_ops": st["diag_ops"], "tile_qubits": st["tile_qubits"],
         "norm_before_renormalize": float(recs[-1]["norm_before"]),
     }
+    if planner is not None:
+        fused_info["planner"] = "learned"
+        fused_info["choice"] = "%s, k_max %d, tile %d" % tuple(recs[-1]["choice"])
+        fused_info["predicted_ms"] = recs[-1]["predicted_ms"]
+    else:
+        fused_info["planner"] = f"greedy, k_max {args.k_max}, tile {args.tile}"
+    fused_info["tile_TFLOPs"] = None
+    if "c64:tile" in kstats and kstats["c64:tile"]["total_ms"]:
+        kt = kstats["c64:tile"]
+        fused_info["tile_TFLOPs"] = kt["flops"] / (kt["total_ms"] / 1e3) / 1e12
+        fused_info["tile_frac_of_mfma_peak"] = fused_info["tile_TFLOPs"] / (MFMA_PEAK["f32"] / 1e12)
     out = {"metric": METRIC, "value": G / fused_e2e, "unit": "gates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -211,7 +281,7 @@ def main():
            "config": {"workload": "qft30: QFT on a seeded basis state then 30 layers of random U3 + "
                                   "CZ brick, 30 qubits, 1815 gates",
                       "n_qubits": n, "gates": G, "fused_dtype": "complex64",
-                      "plain_dtype": "complex128", "planner": "greedy"},
+                      "plain_dtype": "complex128", "planner": fused_info["planner"]},
            "fused_c64": fused_info}
     if plain is not None:
         prun = float(np.mean([r["plain_run_s"] for r in recs]))
@@ -246,8 +316,31 @@ def main():
                           "GBs": v["bytes"] / (v["total_ms"] / 1e3) / 1e9 if v["total_ms"] else None,
                           "TFLOPs": v["flops"] / (v["total_ms"] / 1e3) / 1e12 if v["total_ms"] else None}
                       for k, v in kstats.items()}
+    # outside the timed steps: the greedy planner's classic setting (one
+    # 5-qubit block per pass) as the baseline of the learned choice
+    if planner is not None:
+        from paper_2212_14201_amd import learned_planner
+        gplan = learned_planner.build_plan(ga, n, "c64", learned_planner.GREEDY)
+        fused.init_basis(x)
+        gplan.run(fused)
+        fused.init_basis(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gplan.run(fused)
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1)
+        out["fused_c64"]["greedy_baseline"] = {"setting": "%s, k_max %d, tile %d" % learned_planner.GREEDY,
+                                            "run_ms": gms,
+                                            "learned_speedup": gms / (fused_run * 1e3)}
     del fused, plain
     torch.cuda.empty_cache()
+    out["hbm_copy_GBs"] = copy_bandwidth(torch, 1 << 33)
+    out["fused_c64"]["effective_frac_of_copy"] = out["fused_c64"]["effective_GBs"] / out["hbm_copy_GBs"]
+    if "plain_c128" in out:
+        out["plain_c128"]["frac_of_copy"] = out["plain_c128"]["effective_GBs"] / out["hbm_copy_GBs"]
+    if not args.no_adjoint:
+        out["adjoint_c64"] = adjoint_measure(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, x, gates, args.cpu_seconds, plain_bytes)
     print(json.dumps(out), flush=True)

@@ -54,7 +54,7 @@ typedef enum {
     QVM_ENOMEM = -3,        /* workspace too small, host allocation failed */
     QVM_EDEVICE = -4,       /* HIP runtime or launch error */
     QVM_ESTATE = -5,        /* handle failed earlier, or is in the wrong state */
-    QVM_EUNSUPPORTED = -6   /* valid request this build does not implement */
+    QVM_EUNSUPPORTED = -6   /* valid request the library does not implement */
 } qvm_status;
 
 typedef enum { QVM_C64 = 1, QVM_C128 = 2 } qvm_dtype;

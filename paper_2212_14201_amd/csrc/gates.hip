@@ -34,30 +34,46 @@ template <typename R, int K> struct DenseArgs {
     R m[2 << (2 * K)];               // 2^K x 2^K complex, row-major (re, im)
 };
 
+// Items per thread.  A thread issues the loads of all its items before any
+// arithmetic or store, so that 2^K * U amplitudes per thread are in flight:
+// HBM latency times bandwidth needs about that much outstanding per CU.
+// Items past the end re-read the last item and store nothing.
+template <int K> struct Unroll { static constexpr int U = K == 1 ? 4 : K == 2 ? 2 : 1; };
+constexpr int kTPB = 256;                    // threads per block of the plain kernels
+
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_dense(typename C2<R>::T* __restrict__ psi,
-                                               DenseArgs<R, K> a) {
+__global__ __launch_bounds__(kTPB) void k_dense(typename C2<R>::T* __restrict__ psi,
+                                                DenseArgs<R, K> a) {
     using T = typename C2<R>::T;
-    constexpr int D = 1 << K;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.items; w += stride) {
-        uint64_t b = deposit(w, a.fixed) | a.cmask;
-        T v[D];
+    constexpr int D = 1 << K, U = Unroll<K>::U;
+    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * U) + threadIdx.x;
+    uint64_t b[U];
+    T v[U][D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = psi[b + a.off[j]];
+    for (int u = 0; u < U; ++u) {
+        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, a.items - 1);
+        b[u] = deposit(w, a.fixed) | a.cmask;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[u][j] = psi[b[u] + a.off[j]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (w0 + (uint64_t)kTPB * u >= a.items) break;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             R re = 0, im = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 R mr = a.m[2 * (i * D + j)], mi = a.m[2 * (i * D + j) + 1];
-                re += mr * v[j].x - mi * v[j].y;
-                im += mr * v[j].y + mi * v[j].x;
+                re += mr * v[u][j].x - mi * v[u][j].y;
+                im += mr * v[u][j].y + mi * v[u][j].x;
             }
             T o;
             o.x = re;
             o.y = im;
-            psi[b + a.off[i]] = o;
+            psi[b[u] + a.off[i]] = o;
         }
     }
 }
@@ -69,49 +85,81 @@ template <typename R> struct DiagArgs {
     R d[16];                          // up to 2^3 complex entries
 };
 
+constexpr int kU1 = 8;                       // items per thread, one amplitude per item
+constexpr int kU2 = 4;                       // items per thread, two amplitudes per item
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag(typename C2<R>::T* __restrict__ psi, DiagArgs<R> a) {
+__global__ __launch_bounds__(kTPB) void k_diag(typename C2<R>::T* __restrict__ psi, DiagArgs<R> a) {
     using T = typename C2<R>::T;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.items; w += stride) {
-        uint64_t i = deposit(w, a.cmask) | a.cmask;
+    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU1) + threadIdx.x;
+    uint64_t idx[kU1];
+    T v[kU1];
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) {
+        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, a.items - 1);
+        idx[u] = deposit(w, a.cmask) | a.cmask;
+    }
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) v[u] = psi[idx[u]];
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) {
+        if (w0 + (uint64_t)kTPB * u >= a.items) break;
         int j = 0;
-        for (int r = 0; r < a.k; ++r) j |= (int)((i >> a.t[r]) & 1) << r;
-        T v = psi[i];
-        R dr = a.d[2 * j], di = a.d[2 * j + 1];
+        for (int r = 0; r < a.k; ++r) j |= (int)((idx[u] >> a.t[r]) & 1) << r;
+        const R dr = a.d[2 * j], di = a.d[2 * j + 1];
         T o;
-        o.x = dr * v.x - di * v.y;
-        o.y = dr * v.y + di * v.x;
-        psi[i] = o;
+        o.x = dr * v[u].x - di * v[u].y;
+        o.y = dr * v[u].y + di * v[u].x;
+        psi[idx[u]] = o;
     }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_phase(typename C2<R>::T* __restrict__ psi, uint64_t items,
-                                               uint64_t cmask, uint64_t cval, R pr, R pi) {
+__global__ __launch_bounds__(kTPB) void k_phase(typename C2<R>::T* __restrict__ psi, uint64_t items,
+                                                uint64_t cmask, uint64_t cval, R pr, R pi) {
     using T = typename C2<R>::T;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
-        uint64_t i = deposit(w, cmask) | cval;
-        T v = psi[i];
+    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU1) + threadIdx.x;
+    uint64_t idx[kU1];
+    T v[kU1];
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) {
+        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, items - 1);
+        idx[u] = deposit(w, cmask) | cval;
+    }
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) v[u] = psi[idx[u]];
+#pragma unroll
+    for (int u = 0; u < kU1; ++u) {
+        if (w0 + (uint64_t)kTPB * u >= items) break;
         T o;
-        o.x = pr * v.x - pi * v.y;
-        o.y = pr * v.y + pi * v.x;
-        psi[i] = o;
+        o.x = pr * v[u].x - pi * v[u].y;
+        o.y = pr * v[u].y + pi * v[u].x;
+        psi[idx[u]] = o;
     }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_swappair(typename C2<R>::T* __restrict__ psi, uint64_t items,
-                                                  uint64_t fixed, uint64_t cval, uint64_t xmask) {
+__global__ __launch_bounds__(kTPB) void k_swappair(typename C2<R>::T* __restrict__ psi, uint64_t items,
+                                                   uint64_t fixed, uint64_t cval, uint64_t xmask) {
     using T = typename C2<R>::T;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
-        uint64_t i = deposit(w, fixed) | cval;
-        uint64_t j = i ^ xmask;
-        T a = psi[i], b = psi[j];
-        psi[i] = b;
-        psi[j] = a;
+    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU2) + threadIdx.x;
+    uint64_t idx[kU2];
+    T a[kU2], b[kU2];
+#pragma unroll
+    for (int u = 0; u < kU2; ++u) {
+        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, items - 1);
+        idx[u] = deposit(w, fixed) | cval;
+    }
+#pragma unroll
+    for (int u = 0; u < kU2; ++u) {
+        a[u] = psi[idx[u]];
+        b[u] = psi[idx[u] ^ xmask];
+    }
+#pragma unroll
+    for (int u = 0; u < kU2; ++u) {
+        if (w0 + (uint64_t)kTPB * u >= items) break;
+        psi[idx[u]] = b[u];
+        psi[idx[u] ^ xmask] = a[u];
     }
 }
 
@@ -128,9 +176,11 @@ __global__ __launch_bounds__(256) void k_basis(typename C2<R>::T* __restrict__ p
     }
 }
 
-static unsigned grid_for(uint64_t items) {
-    uint64_t g = (items + 255) / 256;
-    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 20));
+// Blocks that cover `items` work items at `per` items per thread (no grid
+// stride: at most 2^34 amplitudes, so the grid stays below 2^31 blocks).
+static unsigned grid_for(uint64_t items, int per) {
+    const uint64_t g = (items + (uint64_t)kTPB * per - 1) / ((uint64_t)kTPB * per);
+    return (unsigned)std::max<uint64_t>(1, g);
 }
 
 static inline int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -156,7 +206,7 @@ static qvm_status launch_dense_k(qvm_sv* sv, const LOp& op) {
     }
     const double touched = (double)a.items * (1 << K);
     const int tok = prof_begin(sv);
-    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
+    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items, Unroll<K>::U)), dim3(kTPB), 0, sv->stream,
                        (T*)sv->amps, a);
     QVM_LAUNCH_CHECK(sv);
     prof_end(sv, tok, PK_DENSE1 + K - 1, 2.0 * touched * sizeof(T), touched * 8.0 * (1 << K));
@@ -171,7 +221,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
             if (op.phase == cd(1.0, 0.0)) return QVM_OK;   // identity
             uint64_t items = 1ull << (sv->n - popc(op.cond_mask));
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
+            hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items, kU1)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, items, op.cond_mask, op.cond_val,
                                (R)op.phase.real(), (R)op.phase.imag());
             QVM_LAUNCH_CHECK(sv);
@@ -190,7 +240,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
                 a.d[2 * j + 1] = (R)op.m[j].imag();
             }
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items)), dim3(256), 0, sv->stream,
+            hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items, kU1)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, a);
             QVM_LAUNCH_CHECK(sv);
             prof_end(sv, tok, PK_DIAG, 2.0 * a.items * sizeof(T), 6.0 * a.items);
@@ -200,7 +250,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
             uint64_t fixed = op.cond_mask | op.hbit;
             uint64_t items = 1ull << (sv->n - popc(fixed));
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(256), 0, sv->stream,
+            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items, kU2)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
             QVM_LAUNCH_CHECK(sv);
             prof_end(sv, tok, PK_SWAP, 4.0 * items * sizeof(T), 0.0);
@@ -225,10 +275,10 @@ qvm_status launch_init_basis(qvm_sv* sv, uint64_t idx) {
     uint64_t N = 1ull << sv->n;
     const int tok = prof_begin(sv);
     if (sv->dt == QVM_C64)
-        hipLaunchKernelGGL((k_basis<float>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
+        hipLaunchKernelGGL((k_basis<float>), dim3(std::min<unsigned>(grid_for(N, 1), 1u << 20)), dim3(kTPB), 0, sv->stream,
                            (float2*)sv->amps, N, idx);
     else
-        hipLaunchKernelGGL((k_basis<double>), dim3(grid_for(N)), dim3(256), 0, sv->stream,
+        hipLaunchKernelGGL((k_basis<double>), dim3(std::min<unsigned>(grid_for(N, 1), 1u << 20)), dim3(kTPB), 0, sv->stream,
                            (double2*)sv->amps, N, idx);
     QVM_LAUNCH_CHECK(sv);
     prof_end(sv, tok, PK_BASIS, (double)N * (sv->dt == QVM_C64 ? 8 : 16), 0.0);

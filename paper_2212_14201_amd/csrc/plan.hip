@@ -244,8 +244,12 @@ struct Builder {
 };
 
 // Real MFMA fragments of a complex 2^k x 2^k matrix: K = 2^(k+1);
-// fragment (rb, s), lane l holds Mr[16 rb + l % 16][4 s + l / 16] with
-// Mr = [[Re, -Im], [Im, Re]] per complex entry.
+// fragment (rb, s), lane l holds Mr[16 rb + l % 16][col(s, l / 16)] with
+// Mr = [[Re, -Im], [Im, Re]] per complex entry (real index 2 j + part for
+// complex index j).  The contraction index is permuted so that k-steps
+// 2t and 2t+1 take the real and imaginary parts of the same complex input
+// row: col(s, g) = 2 (4 (s / 2) + g) + (s % 2).  A lane then reads each
+// input amplitude as one (re, im) pair.
 template <typename R>
 std::vector<R> fragments(const std::vector<cd>& M, int k) {
     const int dim = 1 << k, K = 2 * dim, RB = K / 16, KS = K / 4;
@@ -261,7 +265,8 @@ std::vector<R> fragments(const std::vector<cd>& M, int k) {
     for (int rb = 0; rb < RB; ++rb)
         for (int s = 0; s < KS; ++s)
             for (int l = 0; l < 64; ++l)
-                f[((size_t)rb * KS + s) * 64 + l] = (R)mr(16 * rb + (l & 15), 4 * s + (l >> 4));
+                f[((size_t)rb * KS + s) * 64 + l] =
+                    (R)mr(16 * rb + (l & 15), 2 * (4 * (s >> 1) + (l >> 4)) + (s & 1));
     return f;
 }
 
@@ -538,8 +543,14 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         pd.c = c;
         pd.nops = (int)ops.size();
         pd.kmax = 0;
-        for (const TOp& o : ops)
-            if (o.type == TOP_BLOCK && o.k > pd.kmax) pd.kmax = o.k;
+        pd.first_block = -1;
+        for (int oi = (int)ops.size() - 1; oi >= 0; --oi) {
+            ops[oi].next_block = pd.first_block;
+            if (ops[oi].type == TOP_BLOCK) {
+                pd.first_block = oi;
+                pd.kmax = std::max(pd.kmax, (int32_t)ops[oi].k);
+            }
+        }
         pd.qmask = qmask;
         pd.ops = ops.empty() ? 0 : B.put(ops.data(), ops.size() * sizeof(TOp));
         std::vector<uint64_t> ldoff((size_t)1 << (L - c));

@@ -36,8 +36,10 @@ template <typename R> struct TT;
 // (checked on gfx950): FP32 rows 4 (l / 16) + r, FP64 rows l / 16 + 4 r.
 typedef float f32v4 __attribute__((ext_vector_type(4)));
 typedef double f64v2 __attribute__((ext_vector_type(2)));
+typedef float f32v2 __attribute__((ext_vector_type(2)));
 template <> struct TT<float> {
     using V4 = f32x4;
+    using V2 = f32v2;                 // one complex64 as (re, im)
     using V16 = f32v4;                // one 16-byte access: two complex64
     static constexpr int EP = 2;      // elements per 16-byte access
     static constexpr int C = 4;       // low bits per tile: 16 x 8 B = 128-byte runs
@@ -45,6 +47,7 @@ template <> struct TT<float> {
 };
 template <> struct TT<double> {
     using V4 = f64x4;
+    using V2 = f64v2;                 // one complex128 as (re, im)
     using V16 = f64v2;                // one 16-byte access: one complex128
     static constexpr int EP = 1;
     static constexpr int C = 3;       // low bits per tile: 8 x 16 B = 128-byte runs
@@ -86,21 +89,24 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
 }
 
 // ---------------------------------------------------------------- blocks
-// The block's real fragments are first copied into LDS (after the tile);
-// every k-step then reads one A value per row block and one B value per
-// column tile from LDS.  Fragment (rb, s), lane l holds
-// Mr[16 rb + l % 16][4 s + l / 16]; B feeds X rows 4 s + l / 16 of column
-// l % 16; the 16x16 result leaves rows out_row(l / 16, r) of column l % 16
-// in register r of lane l.  Each wave owns whole columns, so the in-place
-// update needs no barrier between its reads and writes.
+// The block's real fragments are already in LDS (after the tile; the
+// kernel stages them while the previous op runs); every k-step reads one A
+// value per row block from there.  The
+// contraction index is ordered so that k-steps 2t and 2t+1 take the real
+// and imaginary parts of complex input row 4t + l / 16: lane l reads that
+// amplitude of its column (l % 16) once, as a (re, im) pair, and feeds the
+// two halves to the two k-steps.  The 16x16 result leaves rows
+// out_row(l / 16, r) of column l % 16 in register r of lane l.  Each wave
+// owns whole columns, so the in-place update needs no barrier between its
+// reads and writes.
 //
 // Addressing: the LDS swizzle is linear over GF(2) and the column bits,
 // the lane's row bits and the k-step's row bits are disjoint, so every
 // address is a per-column constant XOR a per-lane constant XOR a
 // wave-uniform term.
 template <typename R, int K>
-__device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ ldsA, const TOp& op,
-                                           const char* __restrict__ blob, int L) {
+__device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
+                                           int L) {
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
@@ -108,11 +114,6 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
     constexpr int CT = RB >= 4 ? 1 : 4 / RB;   // column tiles per wave iteration
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    {
-        const R* __restrict__ frag = (const R*)(blob + op.data);
-        for (int i = threadIdx.x; i < K * K; i += NT) ldsA[i] = frag[i];
-    }
-    __syncthreads();
     int lb[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) lb[r] = op.lb[r];
@@ -129,9 +130,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
     const int ncol = 1 << (L - k);
     const int ntile = (ncol + 15) >> 4;
     const int g = lane >> 4;
-    const int part = g & 1;
-    // B operand: row 2 s + (l / 32): the lane's bit is row bit 0
-    const uint32_t swh = sw((lane >> 5) ? (1u << lb[0]) : 0u);
+    // B operand: complex input row 4 t + g; the lane's share is scat(g)
+    const uint32_t swg = sw(scat(g));
     // epilogue: the lane's share of the output row index
     const int jlane = TT<R>::out_row(g, 0) >> 1;
     const int plane = TT<R>::out_row(g, 0) & 1;
@@ -151,17 +151,21 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, R* __restrict__ 
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[ct][rb] = V4{0, 0, 0, 0};
+        using V2 = typename TT<R>::V2;
 #pragma unroll 2
-        for (int s = 0; s < KS; ++s) {
-            const uint32_t sj = sw(scat(2 * s)) ^ swh;
-            R b[CT];
+        for (int t = 0; t < KS / 2; ++t) {
+            const uint32_t st = sw(scat(4 * t)) ^ swg;
+            V2 b[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds[2 * (swe[ct] ^ sj) + part] : (R)0;
+            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? *(const V2*)(lds + 2 * (swe[ct] ^ st)) : V2{0, 0};
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const R av = Arow[(rb * KS + s) * 64];
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) acc[ct][rb] = mfma16(av, b[ct], acc[ct][rb]);
+                for (int rb = 0; rb < RB; ++rb) {
+                    const R av = Arow[(rb * KS + 2 * t + h) * 64];
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) acc[ct][rb] = mfma16(av, b[ct][h], acc[ct][rb]);
+                }
             }
         }
 #pragma unroll
@@ -300,20 +304,59 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1) void k_tile(R* __restri
     __syncthreads();
 
     const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
+    // fragments: the first block's are copied to LDS with the tile (the
+    // barrier below covers them); each later block's are read into
+    // registers while the block before it runs and stored to LDS after it.
+    if (pd.first_block >= 0) {
+        const TOp& fb = ops[pd.first_block];
+        const R* __restrict__ frag = (const R*)(blob + fb.data);
+        const int kk = 4 << (2 * fb.k);                       // (2^(k+1))^2 reals
+        for (int i = threadIdx.x; i < kk; i += NT) ldsA[i] = frag[i];
+    }
+    __syncthreads();
     for (int oi = 0; oi < pd.nops; ++oi) {
         const TOp& op = ops[oi];
         if (op.type == TOP_BLOCK) {
+            constexpr int PF = 8;                             // prefetch registers per thread
+            R pre[PF];
+            const int nb = op.next_block;
+            const R* __restrict__ nfrag = nullptr;
+            int nkk = 0;
+            if (nb >= 0) {
+                nfrag = (const R*)(blob + ops[nb].data);
+                nkk = 4 << (2 * ops[nb].k);
+                if (nkk <= PF * NT) {
+#pragma unroll
+                    for (int j = 0; j < PF; ++j) {
+                        const int i = threadIdx.x + j * NT;
+                        if (i < nkk) pre[j] = nfrag[i];
+                    }
+                }
+            }
             switch (op.k) {
-                case 3: tile_block<R, 16>(lds, ldsA, op, blob, L); break;
-                case 4: tile_block<R, 32>(lds, ldsA, op, blob, L); break;
-                case 5: tile_block<R, 64>(lds, ldsA, op, blob, L); break;
-                case 6: tile_block<R, 128>(lds, ldsA, op, blob, L); break;
+                case 3: tile_block<R, 16>(lds, ldsA, op, L); break;
+                case 4: tile_block<R, 32>(lds, ldsA, op, L); break;
+                case 5: tile_block<R, 64>(lds, ldsA, op, L); break;
+                case 6: tile_block<R, 128>(lds, ldsA, op, L); break;
                 default: break;
+            }
+            __syncthreads();
+            if (nb >= 0) {
+                if (nkk <= PF * NT) {
+#pragma unroll
+                    for (int j = 0; j < PF; ++j) {
+                        const int i = threadIdx.x + j * NT;
+                        if (i < nkk) ldsA[i] = pre[j];
+                    }
+                } else {
+                    for (int i = threadIdx.x; i < nkk; i += NT) ldsA[i] = nfrag[i];
+                }
+                __syncthreads();
             }
         } else {
             tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // store: per batch, LDS reads first (optionally through the tile-bit
@@ -370,7 +413,10 @@ size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
 template <typename R>
 static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, size_t lds,
                                 double flops) {
-    static bool attr_set[16] = {};
+    static bool attr_set[64][16] = {};       // per device and tile size
+    int dev = 0;
+    QVM_HIP(sv, hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(QVM_EUNSUPPORTED, "device index above 63");
     const unsigned grid = 1u << (sv->n - pd.L);
     const void* fn = nullptr;
     switch (pd.L) {
@@ -383,9 +429,9 @@ static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob
         default: return fail(QVM_EUNSUPPORTED, "tile size outside 3..13");
     }
     if (pd.c != (TT<R>::C < pd.L ? TT<R>::C : pd.L)) return fail(QVM_EARG, "internal: pass low-bit count");
-    if (!attr_set[pd.L]) {
+    if (!attr_set[dev][pd.L]) {
         QVM_HIP(sv, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLdsMax));
-        attr_set[pd.L] = true;
+        attr_set[dev][pd.L] = true;
     }
     R* amps = (R*)sv->amps;
     void* args[] = {(void*)&amps, (void*)&pd, (void*)&blob_dev};

@@ -14,12 +14,10 @@ constexpr size_t kTileLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
 struct TOp {
     int32_t type;
     int32_t k;              // block: matrix width in qubits; diagonal run: number of terms
-    int32_t lb[6];          // local tile bits (block bit r <-> lb[r]); diag: -1 = outer target
-    int32_t ob[6];          // diag: physical bit of an outer target
-    uint64_t lmask, lval;   // condition on local bits (controls, phase pattern)
-    uint64_t omask, oval;   // condition on the tile's fixed (outer) physical bits
+    int32_t lb[6];          // block: local tile bit of block bit r
     uint64_t data;          // byte offset into the plan blob: fragments or DSub[k]
-    double pr, pi;          // phase op factor
+    int32_t next_block;     // index of the pass's next TOP_BLOCK op, -1 if none
+    int32_t pad_;
 };
 
 // One phase term of a diagonal run: amplitudes whose local tile bits match
@@ -39,7 +37,7 @@ struct PassDesc {
     int32_t nops;
     int32_t remap;          // nonzero: store through the remap table
     int32_t kmax;           // widest block in the pass (sizes the LDS fragment area)
-    int32_t pad_;
+    int32_t first_block;    // index of the pass's first TOP_BLOCK op, -1 if none
     uint64_t qmask;         // physical bits that are tile bits
     uint64_t ops;           // byte offset of TOp[nops]
     uint64_t ldoff;         // byte offset of uint64 off[2^(L-c)]: chunk -> physical offset

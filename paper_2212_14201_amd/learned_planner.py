@@ -6,9 +6,10 @@ or tile passes that hold many blocks (``tile = L``).  Which choice is fastest
 depends on the circuit.  The learned planner builds every candidate plan on
 the host, predicts each pass's time with the MLP (features from
 ``qvm_plan_pass_features``), and runs the candidate with the smallest
-predicted total.  The greedy planner with the classic setting (5-qubit
-blocks, one pass each) stays as the fallback and as the judge of plan
-quality; all candidates compute the same state up to rounding.
+predicted total.  The greedy planner alone stays as the fallback (when no
+trained model is present), and at its classic setting (5-qubit blocks, one
+pass each) as the baseline that plan quality is measured against; all
+candidates compute the same state up to rounding.
 
 The MLP is trained on pass timings the simulator measures itself (per-launch
 HIP events of the tile kernel), on seeded random circuits of 26-32 qubits with
@@ -36,9 +37,11 @@ from . import qvm  # noqa: E402
 from .qvm import _i32p, _vp, check, lib  # noqa: E402
 
 NFEAT = 20
+# the trained cost model shipped with the package (complex64 pass timings)
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "costmodel_c64.npz")
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
               ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13), ("tile", 4, 12), ("tile", 3, 11)]
-GREEDY = ("block", 5, 0)       # fallback and judge: 5-qubit blocks, one pass each
+GREEDY = ("block", 5, 0)       # fallback and baseline: 5-qubit blocks, one pass each
 TILE_KIND = 6                  # kernel class index of the tile kernel in the profiler
 
 
@@ -148,9 +151,11 @@ def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_ran
         if (i + 1) % 100 == 0:
             print(f"collect: {i + 1}/{len(jobs)} circuits, {sum(len(t) for t in T)} passes, "
                   f"{time.time() - t0:.0f} s", flush=True)
-    F, T = np.concatenate(F), np.concatenate(T)
-    np.savez_compressed(out_path, features=F, ms=T, seed=np.concatenate(S), cand=np.concatenate(C))
-    return len(T)
+        if (i + 1) % 500 == 0 or i + 1 == len(jobs):
+            # rewritten as it grows, so that a cut-short run keeps what it measured
+            np.savez_compressed(out_path, features=np.concatenate(F), ms=np.concatenate(T),
+                                seed=np.concatenate(S), cand=np.concatenate(C))
+    return sum(len(t) for t in T)
 
 
 # -------------------------------------------------------------------- model
@@ -168,15 +173,26 @@ class LearnedPlanner:
         return float(self.predict_pass_ms(plan_features(plan)).sum())
 
     def choose(self, ga, n, dtype="c64"):
-        """Returns (candidate, plan, predicted ms) with the smallest prediction."""
-        best = None
-        for cand in CANDIDATES:
-            plan = build_plan(ga, n, dtype, cand)
-            if plan is None:
-                continue
-            p = self.predict_plan_ms(plan)
-            if best is None or p < best[2]:
-                best = (cand, plan, p)
+        """Returns (candidate, plan, predicted ms) with the smallest prediction.
+
+        The candidate plans are built on host threads (the library's planner
+        is reentrant and ctypes releases the GIL) and all their passes are
+        scored in one MLP forward."""
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(len(CANDIDATES), os.cpu_count() or 1)) as ex:
+            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c), CANDIDATES))
+        live = [(c, p) for c, p in zip(CANDIDATES, plans) if p is not None]
+        feats = [plan_features(p) for _, p in live]
+        rows = np.concatenate(feats)
+        if len(rows) == 0:                   # nothing to run: every plan is empty
+            return live[0][0], live[0][1], 0.0
+        ms = self.predict_pass_ms(rows)
+        best, o = None, 0
+        for (c, p), f in zip(live, feats):
+            pred = float(ms[o:o + len(f)].sum())
+            o += len(f)
+            if best is None or pred < best[2]:
+                best = (c, p, pred)
         return best
 
     def save(self, path):
@@ -187,6 +203,13 @@ class LearnedPlanner:
         from .costmodel import CostMLP
         net, z = CostMLP.load(path, device)
         return cls(net, z["mu"], z["sd"])
+
+
+def load_default(device="cuda"):
+    """The shipped trained planner, or None when no model file is present."""
+    if not os.path.exists(DEFAULT_MODEL):
+        return None
+    return LearnedPlanner.load(DEFAULT_MODEL, device)
 
 
 def load_rows(*paths):

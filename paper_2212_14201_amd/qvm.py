@@ -88,6 +88,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "paper_2212_14201_amd/build.py (no fallback exists)")
+        # torch first: its HIP runtime has the same soname as the system one,
+        # so the library then binds to the runtime that owns torch's device
+        # memory and streams (one HIP runtime per process).  Loaded the other
+        # way round, two runtimes coexist and the library's may see no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         _declare(L)
         _lib = L

@@ -4,6 +4,7 @@ No call here reaches the GPU: argument errors are returned before anything
 is enqueued, and gate lowering runs on the host.
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -135,3 +136,22 @@ def test_readout_validation():
                               zs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), None,
                               dp, None) == -2
     assert L.qvm_copy_amplitudes(sv.h, 60, 5, dp) == -2
+
+
+def test_one_hip_runtime_in_process():
+    """The binding loads torch before the library, so exactly one HIP runtime
+    (torch's) is mapped: torch's device memory and streams are then valid
+    handles inside the library."""
+    import re
+    import subprocess
+    import sys
+    code = ("import sys, re; sys.path.insert(0, %r)\n"
+            "from paper_2212_14201_amd import qvm\n"
+            "from workloads import Gate\n"
+            "qvm.Plan([Gate('h', (0,))], 3, 'c64', k_max=3)\n"   # first library call, before any torch use
+            "print(sorted(set(re.findall(r'\\S*libamdhip64\\S*', open('/proc/self/maps').read()))))"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs

@@ -81,9 +81,20 @@ def test_layered_28_qubits(path):
     assert zerr <= ptol and zzerr <= ptol
 
 
+def bench_plan(gates, n):
+    """The plan bench.py times: the shipped learned planner's choice, or the
+    greedy planner with 4-qubit blocks in 13-qubit tiles without a model."""
+    from paper_2212_14201_amd import learned_planner
+    planner = learned_planner.load_default()
+    ga = qvm.GateArray(gates)
+    if planner is None:
+        return qvm.Plan(ga, n, "c64", k_max=4, tile_qubits=13)
+    return planner.choose(ga, n, "c64")[1]
+
+
 def test_qft_brick_30_qubits_bench_configuration():
-    """The bench's fused complex64 plan (4-qubit blocks, 13-qubit tiles) and
-    the plain complex128 path on the 30-qubit workload."""
+    """The bench's fused complex64 plan and the plain complex128 path on the
+    30-qubit workload."""
     g = golden("qft30")
     cfg = config_circuit("qft30")
     n, x, gates = cfg["n"], cfg["init"], cfg["gates"]
@@ -91,7 +102,7 @@ def test_qft_brick_30_qubits_bench_configuration():
     idx = np.asarray(g["amp_index"], dtype=np.uint64)
     want = np.asarray(g["amp_re"]) + 1j * np.asarray(g["amp_im"])
     fused = qvm.StateVector(n, "c64", init=x)
-    plan = qvm.Plan(gates, n, "c64", k_max=4, tile_qubits=13)
+    plan = bench_plan(gates, n)
     plan.run(fused)
     ferr = float(np.max(np.abs(fused.gather(idx) - want)))
     fz = float(np.max(np.abs(fused.expect_z_all() - g["z"])))

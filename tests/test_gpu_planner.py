@@ -44,3 +44,41 @@ def test_collect_train_choose(tmp_path):
                                n_range=(13, 15), g_range=(60, 100))
     summ = lp.summarize(recs, checks)
     assert summ["circuits"] == 4 and summ["max_abs_err_vs_c128"] < 1e-5
+
+
+def test_trained_model_gains_over_greedy():
+    """The shipped model against the greedy planner's classic setting (one
+    5-qubit block per pass) on held-out circuits from the training
+    distribution (26-28 qubits, 100-500 gates): measured total time of the
+    learned choices must not exceed the greedy total, and the learned plan's
+    amplitudes must agree with the plain complex128 path."""
+    from paper_2212_14201_amd import qvm
+    planner = lp.load_default()
+    if planner is None:
+        pytest.skip("no trained model shipped")
+    pool = lp.StatePool()
+    learned = greedy = 0.0
+    for s in range(100_000, 100_006):
+        n, gates = random_planner_circuit(s, n_range=(26, 28), g_range=(100, 500))
+        ga = qvm.GateArray(gates)
+        cand, plan, _ = planner.choose(ga, n, "c64")
+        sv = pool.get(n, "c64")
+        lp.time_plan(sv, plan)                        # warm-up
+        lms = lp.time_plan(sv, plan)[0]
+        gms = lp.time_plan(sv, lp.build_plan(ga, n, "c64", lp.GREEDY))[0]
+        print(f"seed {s} n={n} gates={len(gates)} choice={cand}: learned {lms:.2f} ms, greedy {gms:.2f} ms")
+        learned += lms
+        greedy += gms
+    print(f"gain over greedy: {greedy / learned:.2f}x")
+    assert learned <= greedy
+    # the last circuit's learned plan against the plain complex128 path
+    sv.init_basis(0)
+    plan.run(sv)
+    del pool
+    plain = qvm.StateVector(n, "c128", init=0)
+    plain.run(ga)
+    idx = np.random.default_rng(s).integers(0, 1 << n, 4096, dtype=np.uint64)
+    st = plan.stats()
+    tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
+                         + 5 * st["diag_ops"]) * U32
+    assert np.max(np.abs(sv.gather(idx) - plain.gather(idx))) <= tau
