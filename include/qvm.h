@@ -268,9 +268,10 @@ qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* plan);
  * positions >= 20, 13 mean, 14 min, 15 max physical position of block
  * qubits, 16 block qubits on the always-tile low bits, 17 qubits spanned by
  * the blocks' gates (before padding), 18 log2 state bytes, 19 log2 tile
- * count.  out needs cap >= n_passes * QVM_PASS_FEATURES floats (NULL: only
- * *n_passes is set). */
-#define QVM_PASS_FEATURES 20
+ * count, 20 diagonal runs and 21 phase terms that take the angle-
+ * accumulating path.  out needs cap >= n_passes * QVM_PASS_FEATURES floats
+ * (NULL: only *n_passes is set). */
+#define QVM_PASS_FEATURES 22
 qvm_status qvm_plan_pass_features(const qvm_plan* plan, float* out, size_t cap,
                                   int32_t* n_passes);
 

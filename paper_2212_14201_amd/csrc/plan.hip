@@ -243,6 +243,23 @@ struct Builder {
     }
 };
 
+// Runs of at least this many terms take the angle-accumulating path of the
+// tile kernel (one integer add per term and element, then one complex factor
+// per element); shorter runs multiply term by term.  Sign-only runs end in a
+// sign flip instead of a factor, so they pay off sooner.
+constexpr int kTurnsMinTerms = 8;
+constexpr int kTurnsMinSignTerms = 4;
+
+// Angle of a unit-modulus factor as a 64-bit fraction of a full turn,
+// rounded: exp(2 pi i turns / 2^64) = v.
+uint64_t turns_of(cd v) {
+    double a = std::atan2(v.imag(), v.real()) / (2.0 * M_PI);      // (-1/2, 1/2]
+    if (a < 0) a += 1.0;                                            // [0, 1)
+    const double s = std::ldexp(a, 64);
+    if (!(s < 18446744073709551616.0)) return 0;                    // rounded up to a full turn
+    return (uint64_t)std::nearbyint(s);
+}
+
 // Real MFMA fragments of a complex 2^k x 2^k matrix: K = 2^(k+1);
 // fragment (rb, s), lane l holds Mr[16 rb + l % 16][col(s, l / 16)] with
 // Mr = [[Re, -Im], [Im, Re]] per complex entry (real index 2 j + part for
@@ -314,10 +331,16 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         st = gate_matrix(g, p.u);
         if (st) return st;
         const int dim = 1 << p.k;
+        // diagonal: zero off the diagonal and unit-modulus entries (the
+        // diagonal runs apply pure phases); other diagonal matrices are blocks
         p.diag = true;
         for (int r = 0; r < dim && p.diag; ++r)
             for (int cc = 0; cc < dim; ++cc)
-                if (r != cc && p.u[(size_t)r * dim + cc] != cd(0, 0)) { p.diag = false; break; }
+                if (r != cc ? p.u[(size_t)r * dim + cc] != cd(0, 0)
+                            : std::fabs(std::abs(p.u[(size_t)r * dim + cc]) - 1.0) > 1e-12) {
+                    p.diag = false;
+                    break;
+                }
         p.src = (int)i;
         if (popc(p.qmask) > k_max && !p.diag)
             return fail(QVM_EARG, "gate " + std::to_string(i) + " spans more than k_max qubits");
@@ -464,6 +487,12 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             op.type = TOP_DIAGRUN;
             op.k = (int32_t)run.size();
             op.data = B.put(run.data(), run.size() * sizeof(DSub));
+            // long runs accumulate angles (one add per term and element, one
+            // factor per element); short ones multiply term by term
+            bool signs = true;
+            for (const DSub& d : run) signs = signs && d.neg;
+            const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
+            op.flags = (int)run.size() >= at_least ? DRUN_TURNS | (signs ? DRUN_SIGNS : 0) : 0;
             ops.push_back(op);
             run.clear();
         };
@@ -530,6 +559,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                     d.neg = v == cd(-1, 0);
                     d.pr = v.real();
                     d.pi = v.imag();
+                    d.turns = d.neg ? 1ull << 63 : turns_of(v);
                     run.push_back(d);
                 }
                 P->n_diag_ops++;
@@ -670,6 +700,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 } else {
                     ++nruns;
                     nterms += o.k;
+                    if (o.flags & DRUN_TURNS) {
+                        f[20] += 1.f;
+                        f[21] += (float)o.k;
+                    }
                 }
             }
             for (auto& u : pp.units) {

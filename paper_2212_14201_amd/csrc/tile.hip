@@ -137,14 +137,19 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     const int plane = TT<R>::out_row(g, 0) & 1;
     const uint32_t swo = sw(scat(jlane));
     const R* __restrict__ Arow = ldsA + lane;
-    for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
+    // column c = 16 tile + (lane & 15): its LDS slot is the XOR of a per-lane
+    // part and a wave-uniform part (deposit and swizzle are linear over GF(2)
+    // and the two parts occupy disjoint bits)
+    const uint32_t swl = sw(dep32((uint32_t)(lane & 15), bmask));
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    for (int t0 = wv * CT; t0 < ntile; t0 += NW * CT) {
         uint32_t swe[CT];
         bool ok[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            const int c = (t0 + ct) * 16 + (lane & 15);
-            ok[ct] = (t0 + ct) < ntile && c < ncol;
-            swe[ct] = ok[ct] ? sw(dep32((uint32_t)c, bmask)) : 0u;
+            const int ti = t0 + ct;
+            ok[ct] = ti < ntile && ti * 16 + (lane & 15) < ncol;
+            swe[ct] = ok[ct] ? swl ^ sw(dep32(16u * (uint32_t)ti, bmask)) : 0u;
         }
         V4 acc[CT][RB];
 #pragma unroll
@@ -263,9 +268,108 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
     }
 }
 
+// Long runs: every term adds its angle (a fixed-point fraction of a turn,
+// so sums wrap exactly modulo a full turn) to the elements it matches; each
+// element then takes one factor exp(2 pi i acc / 2^bits), or, when every
+// term is a factor of -1, one sign flip.  complex64 keeps 32-bit turns
+// (angle error below 2^-32 turns per term), complex128 64-bit turns.
+template <typename R> struct Turn;
+template <> struct Turn<float> {
+    using T = uint32_t;
+    static __device__ __forceinline__ T from(uint64_t t) { return (uint32_t)((t + (1ull << 31)) >> 32); }
+};
+template <> struct Turn<double> {
+    using T = uint64_t;
+    static __device__ __forceinline__ T from(uint64_t t) { return t; }
+};
+
+// (cos, sin) of 2 pi t / 2^32: the quadrant from the top two bits, the angle
+// inside it folded to [0, pi/4] (sin and cos exchanged past pi/4), then the
+// Taylor series of sin and cos at 0 (truncation below 2e-10 on [0, pi/4]).
+__device__ __forceinline__ void cis_turns(uint32_t t, float& c, float& s) {
+    const uint32_t q = t >> 30;
+    uint32_t f = t & 0x3FFFFFFFu;
+    const bool fold = f > 0x20000000u;
+    f = fold ? 0x40000000u - f : f;
+    const float x = (float)f * 1.4629180792671596e-9f;          // 2 pi / 2^32
+    const float x2 = x * x;
+    const float sn = x * (1.f + x2 * (-1.f / 6 + x2 * (1.f / 120 + x2 * (-1.f / 5040 + x2 * (1.f / 362880)))));
+    const float cs = 1.f + x2 * (-0.5f + x2 * (1.f / 24 + x2 * (-1.f / 720 + x2 * (1.f / 40320 +
+                                                                                  x2 * (-1.f / 3628800)))));
+    const float a = fold ? sn : cs, b = fold ? cs : sn;
+    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
+    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
+}
+
+// The same for 2 pi t / 2^64 in double precision (truncation below 2e-19).
+__device__ __forceinline__ void cis_turns(uint64_t t, double& c, double& s) {
+    const uint32_t q = (uint32_t)(t >> 62);
+    uint64_t f = t & ((1ull << 62) - 1);
+    const bool fold = f > (1ull << 61);
+    f = fold ? (1ull << 62) - f : f;
+    const double x = (double)f * 3.4061215800865545e-19;         // 2 pi / 2^64
+    const double x2 = x * x;
+    const double sn =
+        x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880 +
+        x2 * (-1.0 / 39916800 + x2 * (1.0 / 6227020800.0 + x2 * (-1.0 / 1307674368000.0 +
+        x2 * (1.0 / 355687428096000.0)))))))));
+    const double cs =
+        1.0 + x2 * (-0.5 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320 + x2 * (-1.0 / 3628800 +
+        x2 * (1.0 / 479001600 + x2 * (-1.0 / 87178291200.0 + x2 * (1.0 / 20922789888000.0 +
+        x2 * (-1.0 / 6402373705728000.0)))))))));
+    const double a = fold ? sn : cs, b = fold ? cs : sn;
+    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
+    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
+}
+
+template <typename R, int L>
+__device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DSub* __restrict__ subs,
+                                                   int nsub, uint64_t base, bool signs) {
+    using TU = typename Turn<R>::T;
+    constexpr uint32_t nE = 1u << L;
+    constexpr int NROW = nE >= NT ? (int)(nE / NT) : 1;   // elements per thread
+    constexpr int NPT = NROW < 8 ? NROW : 8;               // elements per sweep
+    constexpr uint32_t LOWM = NT - 1;
+    const uint32_t t = threadIdx.x;
+#pragma unroll 1
+    for (int i0 = 0; i0 < NROW; i0 += NPT) {
+    TU acc[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) acc[i] = 0;
+#pragma unroll 1
+    for (int q = 0; q < nsub; ++q) {
+        const DSub& d = subs[q];
+        if ((base & d.omask) != d.oval) continue;
+        const uint32_t lm = d.lmask, lv = d.lval;
+        const TU a = (t & lm & LOWM) == (lv & LOWM) ? Turn<R>::from(d.turns) : (TU)0;
+        const uint32_t mhi = lm & ~LOWM, vhi = lv & ~LOWM;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) acc[i] += a;
+    }
+    if (t >= nE) return;
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+        const R xr = lds[s], xi = lds[s + 1];
+        if (signs) {
+            // the accumulated angle is 0 or a half turn
+            const R sg = (acc[i] >> (8 * sizeof(TU) - 1)) ? (R)-1 : (R)1;
+            lds[s] = sg * xr;
+            lds[s + 1] = sg * xi;
+        } else {
+            R fr, fi;
+            cis_turns(acc[i], fr, fi);
+            lds[s] = fr * xr - fi * xi;
+            lds[s + 1] = fr * xi + fi * xr;
+        }
+    }
+    }
+}
+
 // ---------------------------------------------------------------- kernel
 template <typename R, int L>
-__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1) void k_tile(R* __restrict__ psi, PassDesc pd,
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
     extern __shared__ __align__(16) char smem[];
     R* lds = (R*)smem;
@@ -354,7 +458,11 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 2 : 1) void k_tile(R* __restri
                 __syncthreads();
             }
         } else {
-            tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+            if (op.flags & DRUN_TURNS)
+                tile_diagrun_turns<R, L>(lds, (const DSub*)(blob + op.data), op.k, base,
+                                         (op.flags & DRUN_SIGNS) != 0);
+            else
+                tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
             __syncthreads();
         }
     }

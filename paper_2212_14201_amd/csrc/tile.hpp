@@ -11,24 +11,32 @@ enum TileOpType : int32_t { TOP_BLOCK = 1, TOP_DIAGRUN = 2 };
 
 constexpr size_t kTileLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
 
+// Diagonal-run flags (TOp::flags).
+enum : int32_t {
+    DRUN_TURNS = 1,         // accumulate each element's phase in turns, one factor per element
+    DRUN_SIGNS = 2          // every term is a factor of -1 (with DRUN_TURNS: a sign flip per element)
+};
+
 struct TOp {
     int32_t type;
     int32_t k;              // block: matrix width in qubits; diagonal run: number of terms
     int32_t lb[6];          // block: local tile bit of block bit r
     uint64_t data;          // byte offset into the plan blob: fragments or DSub[k]
     int32_t next_block;     // index of the pass's next TOP_BLOCK op, -1 if none
-    int32_t pad_;
+    int32_t flags;          // diagonal run: DRUN_* bits
 };
 
 // One phase term of a diagonal run: amplitudes whose local tile bits match
 // (lmask, lval) and whose tile's outer bits match (omask, oval) are
-// multiplied by (pr + i pi); neg marks a factor of exactly -1.
+// multiplied by the unit-modulus factor (pr + i pi) = exp(2 pi i turns / 2^64);
+// neg marks a factor of exactly -1.
 struct DSub {
     uint32_t lmask, lval;
     int32_t neg;
     int32_t pad_;
     uint64_t omask, oval;
     double pr, pi;
+    uint64_t turns;         // the factor's angle as a 64-bit fraction of a full turn
 };
 
 struct PassDesc {

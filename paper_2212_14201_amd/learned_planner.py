@@ -36,7 +36,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from . import qvm  # noqa: E402
 from .qvm import _i32p, _vp, check, lib  # noqa: E402
 
-NFEAT = 20
+NFEAT = 22
 # the trained cost model shipped with the package (complex64 pass timings)
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "costmodel_c64.npz")
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
@@ -202,13 +202,19 @@ class LearnedPlanner:
     def load(cls, path, device="cuda"):
         from .costmodel import CostMLP
         net, z = CostMLP.load(path, device)
+        if net.d != NFEAT:
+            raise ValueError(f"{path}: model takes {net.d} features, the planner emits {NFEAT}")
         return cls(net, z["mu"], z["sd"])
 
 
 def load_default(device="cuda"):
-    """The shipped trained planner, or None when no model file is present."""
+    """The shipped trained planner, or None when no model file is present or
+    it was trained on a different feature layout."""
     if not os.path.exists(DEFAULT_MODEL):
         return None
+    with np.load(DEFAULT_MODEL, allow_pickle=False) as z:
+        if int(z["d"]) != NFEAT:
+            return None
     return LearnedPlanner.load(DEFAULT_MODEL, device)
 
 

@@ -152,3 +152,40 @@ def test_fused_c64_against_plain_c128_at_20_qubits():
     want = oracle.simulate(n, gates, init=x)[idx.astype(np.int64)]
     assert np.max(np.abs(b - want)) <= C128_TOL
     assert np.max(np.abs(a - want)) <= plan_bound(plan)
+
+
+def diagonal_heavy_circuit(n, seed):
+    """H on every qubit, then long runs of diagonal gates between sparse
+    dense layers: random-angle RZ, RZZ and controlled phases, T, S, CZ-only
+    stretches (sign-only runs) and multi-controlled phases, so that runs take
+    both the term-by-term and the angle-accumulating path of the tile kernel,
+    with conditions on tile bits below and above the thread bits and on
+    outer bits."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = [Gate("h", (q,)) for q in range(n)]
+    for layer in range(6):
+        for _ in range(int(rng.integers(3, 25))):
+            kind = int(rng.integers(0, 7))
+            a, b, c = (int(v) for v in rng.choice(n, 3, replace=False))
+            th = float(rng.uniform(0, 2 * math.pi))
+            gates.append([Gate("rz", (a,), (), (th,)), Gate("rzz", (a, b), (), (th,)),
+                          Gate("p", (a,), (b,), (th,)), Gate("t", (a,)), Gate("s", (a,)),
+                          Gate("z", (a,), (b,)), Gate("p", (a,), (b, c), (th,))][kind])
+        if layer % 2:
+            gates += [Gate("z", (q + 1,), (q,)) for q in range(layer % 2, n - 1, 2)] * 2
+            gates += [Gate("z", (q,), (int(rng.integers(0, q)),)) for q in range(1, n)]
+        q = int(rng.integers(0, n))
+        gates.append(Gate("u3", (q,), (), tuple(float(v) for v in rng.uniform(0, 2 * math.pi, 3))))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,tile", [(14, 10), (16, 12), (12, 12)])
+def test_fused_long_diagonal_runs(n, tile, dtype):
+    gates = diagonal_heavy_circuit(n, 900 + n + tile)
+    sv, plan = run_fused(n, gates, dtype, 3, tile, init=0)
+    want = oracle.simulate(n, gates)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+    print(f"n={n} tile={tile} {dtype} {plan.stats()} err={err:.2e} tol={tol:.2e}")
+    assert err <= tol

@@ -137,3 +137,6 @@ def test_pass_features():
         assert F[:, 3:7].sum() == st["blocks"]
         assert F[:, 10].sum() == len(cfg["gates"]) - 15        # swaps are relabelings
         assert np.all(F[:, 18] == 33) and np.all(F[:, 19] == 17)
+        # angle-accumulating runs are a subset of all runs and terms
+        assert np.all(F[:, 20] <= F[:, 8]) and np.all(F[:, 21] <= F[:, 9])
+        assert np.all((F[:, 20] == 0) == (F[:, 21] == 0))
