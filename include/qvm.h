@@ -285,6 +285,22 @@ qvm_status qvm_plan_image(const qvm_plan* plan, void* out, size_t cap, size_t* b
 
 qvm_status qvm_plan_destroy(qvm_plan* plan);
 
+/* Peephole pre-pass before fusion (paper, "Quantum circuit optimization",
+ * first layer: identity pairs removed, consecutive rotations merged).  Two
+ * gates are consecutive when they act on the same qubits and no gate in
+ * between touches any of them.  With identical targets and controls:
+ * H H, X X, Y Y, Z Z, SWAP SWAP, S SDG, T TDG (either order) cancel; I is
+ * dropped; RX, RY, RZ, P and RZZ pairs merge into one gate with the summed
+ * angle (dropped when the sum is exactly 0); T T -> S, TDG TDG -> SDG,
+ * S S -> Z, SDG SDG -> Z; results are compared again with the gate before,
+ * so chains collapse.  Every rule is an exact matrix identity (merged
+ * angles are rounded sums).  Host-only.  Writes the kept gates, in order, to
+ * out (capacity n_in, must not overlap in) and their count to *n_out; the
+ * u pointers of QVM_G_MATRIX gates are copied, so in's matrices must stay
+ * alive as long as out is used.  QVM_EARG / QVM_ERANGE for invalid gates. */
+qvm_status qvm_simplify(const qvm_gate* in, size_t n_in, int n_qubits, qvm_gate* out,
+                        size_t* n_out);
+
 /* ------------------------------------------------------------- gradients */
 
 /* Bytes of device workspace qvm_adjoint_expect_grad needs. */

@@ -150,6 +150,23 @@ class GateArray:
         return ctypes.cast(self.arr, _gp)
 
 
+def simplify(gates, n: int) -> "GateArray":
+    """The library's peephole pre-pass (qvm_simplify): identity pairs removed,
+    consecutive same-axis rotations merged.  Returns a new GateArray that
+    keeps the input's matrix buffers alive."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    L = lib()
+    L.qvm_simplify.argtypes = [_gp, ctypes.c_size_t, ctypes.c_int, _gp, ctypes.POINTER(ctypes.c_size_t)]
+    L.qvm_simplify.restype = ctypes.c_int
+    out = GateArray([])
+    out.arr = (QvmGate * max(1, ga.n))()
+    cnt = ctypes.c_size_t()
+    check(L.qvm_simplify(ga.ptr(), ga.n, int(n), ctypes.cast(out.arr, _gp), ctypes.byref(cnt)))
+    out.n = int(cnt.value)
+    out._keep = [ga]
+    return out
+
+
 def gate_matrix(gate) -> np.ndarray:
     """The library's lowering of one gate (host only)."""
     ga = GateArray([gate])

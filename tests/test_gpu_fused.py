@@ -189,3 +189,21 @@ def test_fused_long_diagonal_runs(n, tile, dtype):
     tol = C128_TOL if dtype == "c128" else plan_bound(plan)
     print(f"n={n} tile={tile} {dtype} {plan.stats()} err={err:.2e} tol={tol:.2e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_simplified_circuit_on_gpu(dtype):
+    """Peephole pre-pass then fused plan on the GPU, against the oracle on
+    the original circuit."""
+    from tests.test_simplify_cpu import redundant_circuit
+    n = 12
+    gates = redundant_circuit(n, 400, 4200)
+    ga = qvm.simplify(gates, n)
+    assert ga.n < len(gates)
+    plan = qvm.Plan(ga, n, dtype, k_max=4, tile_qubits=10)
+    sv = qvm.StateVector(n, dtype, init=5)
+    plan.run(sv)
+    err = float(np.max(np.abs(sv.amplitudes() - oracle.simulate(n, gates, init=5))))
+    tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+    print(f"{dtype}: {len(gates)} -> {ga.n} gates, err {err:.2e} tol {tol:.2e}")
+    assert err <= tol

@@ -140,3 +140,20 @@ def test_pass_features():
         # angle-accumulating runs are a subset of all runs and terms
         assert np.all(F[:, 20] <= F[:, 8]) and np.all(F[:, 21] <= F[:, 9])
         assert np.all((F[:, 20] == 0) == (F[:, 21] == 0))
+
+
+def test_sweep_gate_lists():
+    """The paper-shaped sweep builds valid gates of every kind (checked by
+    the library's own validation when packed) with the stated touched
+    fractions."""
+    sweeps = pytest.importorskip("paper_2212_14201_amd.sweeps")
+    for kind in sweeps.GATE_KINDS:
+        gates = sweeps.gate_list(kind, 12, 16, 5)
+        ga = qvm.GateArray(gates)
+        plan = qvm.Plan(ga, 12, "c64", k_max=3)
+        assert plan.stats()["passes"] >= 1
+        for g in gates:
+            if g.name == "unitary":
+                u = np.asarray(g.matrix)
+                assert np.allclose(u @ u.conj().T, np.eye(u.shape[0]), atol=1e-12)
+    assert sweeps.touched_fraction("toffoli") == 0.25
