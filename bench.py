@@ -109,15 +109,18 @@ def cpu_baseline(n, x, gates, budget_s, plain_bytes_fn):
 
 
 def copy_bandwidth(torch, nbytes, reps=3):
-    """A plain device-to-device copy of nbytes (read + write), in GB/s: the
-    measured streaming ceiling beside the 8 TB/s peak."""
+    """The library's streaming device copy (qvm_stream_copy) of nbytes, read
+    plus written, in GB/s: the measured streaming reference beside the 8 TB/s
+    peak."""
+    from paper_2212_14201_amd import qvm
     src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    stream = torch.cuda.current_stream().cuda_stream
+    qvm.stream_copy(dst, src, stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        qvm.stream_copy(dst, src, stream)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps

@@ -354,6 +354,14 @@ qvm_status qvm_mlp_adam_step(size_t n_params, float* params, const float* grads,
 
 /* --------------------------------------------------------------- timing */
 
+/* Streaming device copy of `bytes` from src to dst (device pointers, 16-byte
+ * aligned, bytes a multiple of 16, not overlapping), asynchronous on
+ * `stream`: the measured bandwidth reference that effective GB/s figures are
+ * compared with beside the HBM peak (a STREAM-style copy; no paper
+ * counterpart).  QVM_EARG for NULL, misaligned or overlapping buffers. */
+qvm_status qvm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+
 /* Per-launch kernel timing for one state: between qvm_profile_begin and
  * qvm_profile_end every kernel the library launches for the state is
  * bracketed by two HIP events recorded on the state's stream.  The

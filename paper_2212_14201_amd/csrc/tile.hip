@@ -368,6 +368,8 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DS
 }
 
 // ---------------------------------------------------------------- kernel
+// The tile is read and written once per pass with nontemporal accesses (the
+// state streams through; caching it in L2 gains nothing).
 template <typename R, int L>
 __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
@@ -397,7 +399,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 g[it] = base + ldoff[e >> C] + (e & CM);
             }
 #pragma unroll
-            for (int it = 0; it < BATCH; ++it) v[it] = *(const V16*)(psi + 2 * g[it]);
+            for (int it = 0; it < BATCH; ++it) v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * g[it]));
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
                 const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
                 const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
-                *(V16*)(psi + 2 * (base + ldoff[e >> C] + (e & CM))) = v[it];
+                __builtin_nontemporal_store(v[it], (V16*)(psi + 2 * (base + ldoff[e >> C] + (e & CM))));
             }
         }
     }

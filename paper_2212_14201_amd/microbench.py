@@ -7,6 +7,7 @@ counters for a plain device copy of known size (the scale factor).
     python -m paper_2212_14201_amd.microbench --kernel dense1 --n 30 --dtype c128
     python -m paper_2212_14201_amd.microbench --kernel tile --n 30 --dtype c64
     python -m paper_2212_14201_amd.microbench --kernel copy --n 30 --dtype c128
+    python -m paper_2212_14201_amd.microbench --kernel stream --n 30 --launches 5
 """
 import argparse
 import os
@@ -17,7 +18,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=["dense1", "tile", "copy"], required=True)
+    ap.add_argument("--kernel", choices=["dense1", "tile", "copy", "stream"], required=True)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--launches", type=int, default=3)
@@ -26,6 +27,43 @@ def main():
     from paper_2212_14201_amd import qvm
     from workloads import Gate, config_circuit
 
+    if a.kernel == "stream":
+        # streaming rates: qvm_stream_copy, a plain U3 on complex128 and an
+        # almost empty tile pass on complex64, each at 2^n amplitudes
+        def timed(fn, reps):
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+        nb = 16 << a.n
+        src = torch.zeros(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        ms = timed(lambda: qvm.stream_copy(dst, src), a.launches)
+        print(f"qvm_stream_copy {nb >> 30} GiB: {ms:.3f} ms, {2 * nb / ms / 1e6:.0f} GB/s", flush=True)
+        ms = timed(lambda: dst.copy_(src), a.launches)
+        print(f"torch device copy {nb >> 30} GiB: {ms:.3f} ms, {2 * nb / ms / 1e6:.0f} GB/s", flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
+        sv = qvm.StateVector(a.n, "c128", init=0)
+        for t in (0, a.n // 3, a.n - 1):
+            g = qvm.GateArray([Gate("u3", (t,), (), (0.3, 0.2, 0.1))])
+            ms = timed(lambda: sv.run(g), a.launches)
+            print(f"plain u3 complex128 target {t}: {ms:.3f} ms, {2 * 16 * 2**a.n / ms / 1e6:.0f} GB/s", flush=True)
+        del sv
+        torch.cuda.empty_cache()
+        sv = qvm.StateVector(a.n, "c64", init=0)
+        plan = qvm.Plan([Gate("z", (a.n - 1,), (a.n - 2,))], a.n, "c64", k_max=3, tile_qubits=13)
+        def run():
+            sv.init_basis(0)
+            plan.run(sv)
+        ms = timed(run, a.launches) - timed(lambda: sv.init_basis(0), a.launches)
+        print(f"tile pass complex64 (one CZ): {ms:.3f} ms, {2 * 8 * 2**a.n / ms / 1e6:.0f} GB/s", flush=True)
+        return
     if a.kernel == "copy":
         real = torch.float32 if a.dtype == "c64" else torch.float64
         src = torch.zeros(2 << a.n, dtype=real, device="cuda")

@@ -167,6 +167,20 @@ def simplify(gates, n: int) -> "GateArray":
     return out
 
 
+def stream_copy(dst, src, stream=None):
+    """qvm_stream_copy between two torch device tensors of equal byte size."""
+    import torch
+    L = lib()
+    L.qvm_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+    L.qvm_stream_copy.restype = ctypes.c_int
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("stream_copy: sizes differ")
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+    check(L.qvm_stream_copy(dst.data_ptr(), src.data_ptr(), nb, stream))
+
+
 def gate_matrix(gate) -> np.ndarray:
     """The library's lowering of one gate (host only)."""
     ga = GateArray([gate])

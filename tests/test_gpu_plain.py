@@ -176,3 +176,15 @@ def test_init_basis_and_determinism():
     assert amp[-1] == 1 and np.count_nonzero(amp) == 1
     with pytest.raises(qvm.QvmError):
         sv.init_basis(1 << n)
+
+
+def test_stream_copy_is_exact():
+    import torch
+    for nbytes in (16, 4096 + 16, 3 << 20):
+        src = torch.randint(-2**31, 2**31 - 1, (nbytes // 4,), dtype=torch.int32, device="cuda")
+        dst = torch.zeros_like(src)
+        qvm.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    with pytest.raises(qvm.QvmError):
+        qvm.stream_copy(src[1:], src[:-1])                  # overlapping and misaligned
