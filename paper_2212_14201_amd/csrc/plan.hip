@@ -260,6 +260,41 @@ uint64_t turns_of(cd v) {
     return (uint64_t)std::nearbyint(s);
 }
 
+// Address table of a block op (layout in tile.hpp): the wave-uniform parts
+// of its LDS slots, computed once here instead of per access in the kernel.
+std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt) {
+    auto rows = [&](int j) {                     // block row index -> tile bits
+        uint32_t e = 0;
+        for (int q = 0; q < k; ++q)
+            if ((j >> q) & 1) e |= 1u << lb[q];
+        return e;
+    };
+    uint32_t bmask = 0;
+    for (int q = 0; q < k; ++q) bmask |= 1u << lb[q];
+    auto deposit = [&](uint32_t w) {             // w over the tile bits outside the block
+        uint32_t e = 0;
+        for (int i = 0, b = 0; i < L; ++i) {
+            if ((bmask >> i) & 1) continue;
+            if ((w >> b) & 1) e |= 1u << i;
+            ++b;
+        }
+        return e;
+    };
+    const BlockTabLayout lay(L, k);
+    std::vector<uint32_t> t((size_t)lay.words(), 0u);
+    for (int ti = 0; ti < lay.ntile; ++ti) t[lay.col() + ti] = tile_swizzle(deposit(16u * ti));
+    for (int i = 0; i < lay.nb; ++i) t[lay.brow() + i] = tile_swizzle(rows(4 * i));
+    for (int rb = 0; rb < lay.ne / 4; ++rb)
+        for (int r = 0; r < 4; ++r) {
+            // complex64: registers (2h, 2h+1) hold output row 8 rb + h (plus
+            // the lane's 2 (l / 16)); complex128: register r holds row
+            // 8 rb + 2 r (plus the lane's (l / 16) / 2)
+            const int j = dt == QVM_C64 ? (r < 2 ? 8 * rb + r : -1) : 8 * rb + 2 * r;
+            t[lay.erow() + 4 * rb + r] = j < 0 ? 0u : tile_swizzle(rows(j));
+        }
+    return t;
+}
+
 // Real MFMA fragments of a complex 2^k x 2^k matrix: K = 2^(k+1);
 // fragment (rb, s), lane l holds Mr[16 rb + l % 16][col(s, l / 16)] with
 // Mr = [[Re, -Im], [Im, Re]] per complex entry (real index 2 j + part for
@@ -516,6 +551,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 op.type = TOP_BLOCK;
                 op.k = k;
                 for (int r = 0; r < k; ++r) op.lb[r] = local_of_wire[bq[r]];
+                {
+                    const std::vector<uint32_t> tab = block_table(op.lb, k, L, dt);
+                    op.tab = B.put(tab.data(), tab.size() * sizeof(uint32_t));
+                }
                 if (dt == QVM_C64) {
                     auto f = fragments<float>(M, k);
                     op.data = B.put(f.data(), f.size() * sizeof(float));
@@ -560,6 +599,12 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                     d.pr = v.real();
                     d.pi = v.imag();
                     d.turns = d.neg ? 1ull << 63 : turns_of(v);
+                    {
+                        const uint32_t hi = ~(uint32_t)(kTileThreads - 1);
+                        const int nrow = L > 9 ? 1 << (L - 9) : 1;          // elements per thread
+                        for (int i = 0; i < nrow; ++i)
+                            if ((((uint32_t)kTileThreads * i) & d.lmask & hi) == (d.lval & hi)) d.rows |= 1u << i;
+                    }
                     run.push_back(d);
                 }
                 P->n_diag_ops++;

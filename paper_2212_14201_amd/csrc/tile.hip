@@ -20,12 +20,14 @@
 //              elements held in registers.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "tile.hpp"
 
 namespace qvm {
 
-constexpr int NT = 512;               // threads per tile workgroup (8 waves)
+constexpr int NT = kTileThreads;      // threads per tile workgroup (8 waves)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -61,12 +63,7 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// LDS slot of tile element e: bits 1..3 are XOR-ed with bits 4..6 and 8..10
-// so that column walks with large strides spread over banks; bit 0 is kept,
-// so pairs (2m, 2m+1) stay adjacent for 16-byte accesses.
-__device__ __forceinline__ uint32_t sw(uint32_t e) {
-    return e ^ ((((e >> 4) ^ (e >> 8)) & 7u) << 1);
-}
+__device__ __forceinline__ uint32_t sw(uint32_t e) { return tile_swizzle(e); }
 
 __device__ __forceinline__ uint32_t dep32(uint32_t w, uint32_t fixed) {
     while (fixed) {
@@ -106,7 +103,7 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
 // wave-uniform term.
 template <typename R, int K>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
-                                           int L) {
+                                           const char* __restrict__ blob, int L) {
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
@@ -130,26 +127,28 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     const int ncol = 1 << (L - k);
     const int ntile = (ncol + 15) >> 4;
     const int g = lane >> 4;
-    // B operand: complex input row 4 t + g; the lane's share is scat(g)
+    // The slots are linear in the bits they are built from, so each address
+    // is a wave-uniform part from the block's table (scalar loads) XOR a
+    // per-lane part computed once here.
+    const BlockTabLayout lay(L, k);
+    const uint32_t* __restrict__ tab = (const uint32_t*)(blob + op.tab);
+    // B operand: complex input row 4 t + g; the lane's share is rows(g)
     const uint32_t swg = sw(scat(g));
     // epilogue: the lane's share of the output row index
     const int jlane = TT<R>::out_row(g, 0) >> 1;
     const int plane = TT<R>::out_row(g, 0) & 1;
     const uint32_t swo = sw(scat(jlane));
-    const R* __restrict__ Arow = ldsA + lane;
-    // column c = 16 tile + (lane & 15): its LDS slot is the XOR of a per-lane
-    // part and a wave-uniform part (deposit and swizzle are linear over GF(2)
-    // and the two parts occupy disjoint bits)
+    // the lane's column inside a column tile
     const uint32_t swl = sw(dep32((uint32_t)(lane & 15), bmask));
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    for (int t0 = wv * CT; t0 < ntile; t0 += NW * CT) {
+    const R* __restrict__ Arow = ldsA + lane;
+    for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
         uint32_t swe[CT];
         bool ok[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            const int ti = t0 + ct;
-            ok[ct] = ti < ntile && ti * 16 + (lane & 15) < ncol;
-            swe[ct] = ok[ct] ? swl ^ sw(dep32(16u * (uint32_t)ti, bmask)) : 0u;
+            const int c = (t0 + ct) * 16 + (lane & 15);
+            ok[ct] = (t0 + ct) < ntile && c < ncol;
+            swe[ct] = ok[ct] ? swl ^ tab[lay.col() + min(t0 + ct, ntile - 1)] : 0u;
         }
         V4 acc[CT][RB];
 #pragma unroll
@@ -159,7 +158,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
         using V2 = typename TT<R>::V2;
 #pragma unroll 2
         for (int t = 0; t < KS / 2; ++t) {
-            const uint32_t st = sw(scat(4 * t)) ^ swg;
+            const uint32_t st = tab[lay.brow() + t] ^ swg;
             V2 b[CT];
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? *(const V2*)(lds + 2 * (swe[ct] ^ st)) : V2{0, 0};
@@ -183,14 +182,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                     // complex rows 8 rb + 2 g and 8 rb + 2 g + 1
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
-                        const uint32_t sl = swe[ct] ^ swo ^ sw(scat(8 * rb + hh));
+                        const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + hh];
                         *(float2*)(lds + 2 * sl) = make_float2(acc[ct][rb][2 * hh], acc[ct][rb][2 * hh + 1]);
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int iu = 16 * rb + TT<R>::out_row(0, r);   // wave-uniform row bits
-                        const uint32_t sl = swe[ct] ^ swo ^ sw(scat(iu >> 1));
+                        const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + r];
                         lds[2 * sl + plane] = acc[ct][rb][r];
                     }
                 }
@@ -230,15 +228,14 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
         for (int q = 0; q < nsub; ++q) {
             const DSub& d = subs[q];
             if ((base & d.omask) != d.oval) continue;
-            const uint32_t lm = d.lmask, lv = d.lval;
-            const bool hlo = (t & lm & LOWM) == (lv & LOWM);
-            const uint32_t mhi = lm & ~LOWM, vhi = lv & ~LOWM;
+            const bool hlo = (t & d.lmask & LOWM) == (d.lval & LOWM);
+            const uint32_t rows = d.rows >> i0;     // bit i: element i of this sweep matches
             if (d.neg) {
                 // factor -1 where the low bits match: a sign flip
                 const R sg = hlo ? (R)-1 : (R)1;
 #pragma unroll
                 for (int i = 0; i < NPT; ++i) {
-                    if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) {
+                    if ((rows >> i) & 1) {
                         xr[i] *= sg;
                         xi[i] *= sg;
                     }
@@ -250,7 +247,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
             const R fi = hlo ? (R)d.pi : (R)0;
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
-                if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) {
+                if ((rows >> i) & 1) {
                     const R a = xr[i], b = xi[i];
                     xr[i] = fr * a - fi * b;
                     xi[i] = fr * b + fi * a;
@@ -340,12 +337,16 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DS
     for (int q = 0; q < nsub; ++q) {
         const DSub& d = subs[q];
         if ((base & d.omask) != d.oval) continue;
-        const uint32_t lm = d.lmask, lv = d.lval;
-        const TU a = (t & lm & LOWM) == (lv & LOWM) ? Turn<R>::from(d.turns) : (TU)0;
-        const uint32_t mhi = lm & ~LOWM, vhi = lv & ~LOWM;
+        const TU tv = Turn<R>::from(d.turns);
+        const TU a = (t & d.lmask & LOWM) == (d.lval & LOWM) ? tv : (TU)0;
+        const uint32_t rows = d.rows >> i0;
+        // all-ones or zero per element (one scalar bit extract), so the add
+        // needs no per-element branch or compare
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            if (((NT * (uint32_t)(i0 + i)) & mhi) == vhi) acc[i] += a;
+        for (int i = 0; i < NPT; ++i) {
+            const TU m = (TU)(-(typename std::make_signed<TU>::type)((rows >> i) & 1));
+            acc[i] += a & m;
+        }
     }
     if (t >= nE) return;
 #pragma unroll
@@ -374,7 +375,10 @@ template <typename R, int L>
 __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
     extern __shared__ __align__(16) char smem[];
-    R* lds = (R*)smem;
+    // LDS: the widest block's fragments first (their reads then take
+    // constant offsets from a per-lane base), the tile after them
+    R* ldsA = (R*)smem;
+    R* lds = ldsA + (pd.kmax >= 3 ? 4u << (2 * pd.kmax) : 0u);
     constexpr int EP = TT<R>::EP;
     constexpr int C = TT<R>::C < L ? TT<R>::C : L;          // low bits in every tile
     constexpr uint32_t NP = (1u << L) / EP;                  // 16-byte pieces per tile
@@ -382,7 +386,6 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     constexpr int BATCH = NIT < 4 ? NIT : 4;
     constexpr uint32_t CM = (1u << C) - 1;
     using V16 = typename TT<R>::V16;
-    R* ldsA = lds + (2u << L);               // block fragments follow the tile
     const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
     const uint64_t* __restrict__ ldoff = (const uint64_t*)(blob + pd.ldoff);
     const bool live = threadIdx.x < NP;
@@ -440,10 +443,10 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 }
             }
             switch (op.k) {
-                case 3: tile_block<R, 16>(lds, ldsA, op, L); break;
-                case 4: tile_block<R, 32>(lds, ldsA, op, L); break;
-                case 5: tile_block<R, 64>(lds, ldsA, op, L); break;
-                case 6: tile_block<R, 128>(lds, ldsA, op, L); break;
+                case 3: tile_block<R, 16>(lds, ldsA, op, blob, L); break;
+                case 4: tile_block<R, 32>(lds, ldsA, op, blob, L); break;
+                case 5: tile_block<R, 64>(lds, ldsA, op, blob, L); break;
+                case 6: tile_block<R, 128>(lds, ldsA, op, blob, L); break;
                 default: break;
             }
             __syncthreads();

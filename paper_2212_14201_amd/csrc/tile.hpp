@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include <hip/hip_runtime.h>
+
 namespace qvm {
 
 enum TileOpType : int32_t { TOP_BLOCK = 1, TOP_DIAGRUN = 2 };
@@ -24,20 +26,59 @@ struct TOp {
     uint64_t data;          // byte offset into the plan blob: fragments or DSub[k]
     int32_t next_block;     // index of the pass's next TOP_BLOCK op, -1 if none
     int32_t flags;          // diagonal run: DRUN_* bits
+    uint64_t tab;           // block: byte offset of its address table (BlockTab layout)
 };
+
+// LDS slot of tile element e: bits 1..3 are XOR-ed with bits 4..6 and 8..10
+// so that column walks with large strides spread over banks; bit 0 is kept,
+// so pairs (2m, 2m+1) stay adjacent for 16-byte accesses.  The map is linear
+// over GF(2): slot(a ^ b) = slot(a) ^ slot(b).
+__host__ __device__ inline uint32_t tile_swizzle(uint32_t e) {
+    return e ^ ((((e >> 4) ^ (e >> 8)) & 7u) << 1);
+}
+
+// Address table of a block op (uint32 words, LDS slots before the complex
+// stride): the wave-uniform parts of the block's LDS addresses, so that the
+// kernel forms each address with one XOR per access.
+//   col[ti], ti < ntile = ceil(2^(L-k) / 16): slot(deposit(16 ti)) over the
+//            tile bits outside the block (the column tile's base)
+//   brow[t], t < K/8:  slot(rows(4 t)), the input rows of k-step pair t
+//   erow[4 rb + r], rb < K/16, r < 4: slot of the output rows a lane's
+//            register r of row block rb holds, without the lane's own share
+// rows(j) places block row index j on the block's tile bits lb[].
+struct BlockTabLayout {
+    int ntile, nb, ne;
+    __host__ __device__ BlockTabLayout(int L, int k) {
+        const int ncol = 1 << (L - k);
+        ntile = (ncol + 15) >> 4;
+        nb = (2 << k) / 8;
+        ne = 4 * ((2 << k) / 16);
+    }
+    __host__ __device__ int col() const { return 0; }
+    __host__ __device__ int brow() const { return ntile; }
+    __host__ __device__ int erow() const { return ntile + nb; }
+    __host__ __device__ int words() const { return ntile + nb + ne; }
+};
+
+constexpr int kTileThreads = 512;    // threads per tile workgroup (8 waves)
 
 // One phase term of a diagonal run: amplitudes whose local tile bits match
 // (lmask, lval) and whose tile's outer bits match (omask, oval) are
 // multiplied by the unit-modulus factor (pr + i pi) = exp(2 pi i turns / 2^64);
-// neg marks a factor of exactly -1.
+// neg marks a factor of exactly -1.  Thread t of the tile workgroup holds
+// elements t + kTileThreads i; bit i of rows is set when the bits of
+// kTileThreads i match the term's condition on the local bits above the
+// thread bits (the part of the test that is uniform across the workgroup).
 struct DSub {
     uint32_t lmask, lval;
     int32_t neg;
-    int32_t pad_;
+    uint32_t rows;
     uint64_t omask, oval;
     double pr, pi;
     uint64_t turns;         // the factor's angle as a 64-bit fraction of a full turn
+    uint64_t pad2_;         // 64 bytes: read as four 16-byte words
 };
+static_assert(sizeof(DSub) == 64, "DSub is read as four 16-byte words");
 
 struct PassDesc {
     int32_t L;              // tile qubits

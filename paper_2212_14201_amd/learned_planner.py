@@ -12,8 +12,10 @@ pass each) as the baseline that plan quality is measured against; all
 candidates compute the same state up to rounding.
 
 The MLP is trained on pass timings the simulator measures itself (per-launch
-HIP events of the tile kernel), on seeded random circuits of 26-32 qubits with
-100-500 gates drawn from {H, T, RX, RZ, RZZ, CNOT, CZ, Toffoli}.
+HIP events of the tile kernel), on a seeded mixture of circuit families
+(``workloads.planner_mix_circuit``: random gates from {H, T, RX, RZ, RZZ, CNOT,
+CZ, Toffoli}, layered U3 + CZ bricks, QFT prefixes, rotation + CNOT layers;
+26-32 qubits).  Features are clamped to the training range when predicting.
 
     python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 2000 --out D.npz
     python -m paper_2212_14201_amd.learned_planner train    --data D.npz --model M.npz
@@ -122,15 +124,29 @@ def planner_circuit(seed, n_range=(26, 32), g_range=(100, 500)):
     return random_planner_circuit(seed, n_range=n_range, g_range=g_range)
 
 
+# circuits longer than this are timed with tile-pass candidates only (one
+# block per pass would take seconds per circuit); block passes are covered
+# by the shorter circuits, and a block pass looks the same in either
+LONG_CIRCUIT = 600
+
+
 # ------------------------------------------------------------------ collect
-def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_range=(100, 500)):
+def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_range=(100, 500), mix=True):
     """Time one random candidate plan per circuit; save every pass's features
-    and measured milliseconds (npz: features, ms, seed, cand)."""
+    and measured milliseconds (npz: features, ms, seed, cand).  mix: circuits
+    from the mixture of families (``workloads.planner_mix_circuit``), else
+    the random planner workload with the given ranges."""
+    from workloads import planner_mix_circuit
     rng = np.random.Generator(np.random.PCG64(seed + first))
+    tiles = [c for c in CANDIDATES if c[0] == "tile"]
     jobs = []
     for s in range(first, first + count):
-        n, gates = planner_circuit(s, n_range, g_range)
-        jobs.append((n, s, gates, CANDIDATES[int(rng.integers(0, len(CANDIDATES)))]))
+        if mix:
+            n, gates, _ = planner_mix_circuit(s)
+        else:
+            n, gates = planner_circuit(s, n_range, g_range)
+        pool = tiles if len(gates) > LONG_CIRCUIT else CANDIDATES
+        jobs.append((n, s, gates, pool[int(rng.integers(0, len(pool)))]))
     jobs.sort(key=lambda j: j[0])          # group by size to reuse the state buffer
     pool = StatePool()
     F, T, S, C = [], [], [], []
@@ -160,11 +176,17 @@ def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_ran
 
 # -------------------------------------------------------------------- model
 class LearnedPlanner:
-    def __init__(self, net, mu, sd):
+    def __init__(self, net, mu, sd, lo=None, hi=None):
         self.net, self.mu, self.sd = net, mu, sd
+        self.lo, self.hi = lo, hi
 
     def predict_pass_ms(self, feats):
+        """Predicted ms per pass.  Features are clamped to the range seen in
+        training, so a pass beyond it is predicted like the nearest trained
+        one instead of by the network's extrapolation."""
         import torch
+        if self.lo is not None:
+            feats = np.clip(feats, self.lo, self.hi)
         X = torch.tensor((feats - self.mu) / self.sd, dtype=torch.float32, device=self.net.device)
         y = self.net.predict(X).cpu().numpy().astype(np.float64)
         return np.exp(y)
@@ -196,7 +218,10 @@ class LearnedPlanner:
         return best
 
     def save(self, path):
-        self.net.save(path, extra={"mu": self.mu, "sd": self.sd})
+        extra = {"mu": self.mu, "sd": self.sd}
+        if self.lo is not None:
+            extra.update(lo=self.lo, hi=self.hi)
+        self.net.save(path, extra=extra)
 
     @classmethod
     def load(cls, path, device="cuda"):
@@ -204,7 +229,9 @@ class LearnedPlanner:
         net, z = CostMLP.load(path, device)
         if net.d != NFEAT:
             raise ValueError(f"{path}: model takes {net.d} features, the planner emits {NFEAT}")
-        return cls(net, z["mu"], z["sd"])
+        lo = z["lo"] if "lo" in z.files else None
+        hi = z["hi"] if "hi" in z.files else None
+        return cls(net, z["mu"], z["sd"], lo, hi)
 
 
 def load_default(device="cuda"):
@@ -250,17 +277,22 @@ def train(F, T, epochs=60, batch=4096, lr=2e-3, hidden=128, seed=0, device="cuda
         hist.append(tot / nb)
         if log and (ep % 10 == 0 or ep == epochs - 1):
             print(f"train: epoch {ep} loss {hist[-1]:.4f}", flush=True)
-    return LearnedPlanner(net, mu, sd), hist
+    return LearnedPlanner(net, mu, sd, F.min(axis=0), F.max(axis=0)), hist
 
 
 # ----------------------------------------------------------------- evaluate
 def evaluate(planner, first, count, dtype="c64", all_cands=50, check_amplitudes=8, n_range=(26, 32),
-             g_range=(100, 500)):
+             g_range=(100, 500), mix=False):
     """Held-out circuits: measured time of the learned choice against the
     greedy planner (5-qubit blocks, one pass each), the best fixed setting
-    and, for the first `all_cands` circuits, every candidate."""
+    and, for the first `all_cands` circuits, every candidate.  mix: circuits
+    from the family mixture instead of the random planner workload."""
     import torch
-    jobs = [(planner_circuit(s, n_range, g_range), s) for s in range(first, first + count)]
+    from workloads import planner_mix_circuit
+    if mix:
+        jobs = [(planner_mix_circuit(s)[:2], s) for s in range(first, first + count)]
+    else:
+        jobs = [(planner_circuit(s, n_range, g_range), s) for s in range(first, first + count)]
     jobs.sort(key=lambda j: j[0][0])
     pool = StatePool()
     recs = []
@@ -341,9 +373,11 @@ def main():
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--all-cands", type=int, default=50)
     ap.add_argument("--report", default="gpurun_out/planner_eval.json")
+    ap.add_argument("--no-mix", action="store_true", help="collect: the random planner workload only")
+    ap.add_argument("--mix", action="store_true", help="evaluate: circuits from the family mixture")
     a = ap.parse_args()
     if a.cmd == "collect":
-        rows = collect(a.first, a.count, a.out)
+        rows = collect(a.first, a.count, a.out, mix=not a.no_mix)
         print(f"collected {rows} pass timings", flush=True)
     elif a.cmd == "train":
         F, T = load_rows(*a.data)
@@ -352,7 +386,7 @@ def main():
         print(json.dumps({"rows": len(F), "final_loss": hist[-1]}), flush=True)
     else:
         planner = LearnedPlanner.load(a.model)
-        recs, checks = evaluate(planner, a.first, a.count, all_cands=a.all_cands)
+        recs, checks = evaluate(planner, a.first, a.count, all_cands=a.all_cands, mix=a.mix)
         summ = summarize(recs, checks)
         with open(a.report, "w") as fh:
             json.dump({"summary": summ, "records": recs, "checks": checks}, fh)

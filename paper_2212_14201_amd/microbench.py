@@ -8,6 +8,7 @@ counters for a plain device copy of known size (the scale factor).
     python -m paper_2212_14201_amd.microbench --kernel tile --n 30 --dtype c64
     python -m paper_2212_14201_amd.microbench --kernel copy --n 30 --dtype c128
     python -m paper_2212_14201_amd.microbench --kernel stream --n 30 --launches 5
+    python -m paper_2212_14201_amd.microbench --kernel blocks --k 4 --blocks 32 --n 30 --launches 2
 """
 import argparse
 import os
@@ -18,7 +19,9 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=["dense1", "tile", "copy", "stream"], required=True)
+    ap.add_argument("--kernel", choices=["dense1", "tile", "copy", "stream", "blocks"], required=True)
+    ap.add_argument("--k", type=int, default=4, help="blocks: block width in qubits")
+    ap.add_argument("--blocks", type=int, default=32, help="blocks: fused blocks in the one tile pass")
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--launches", type=int, default=3)
@@ -63,6 +66,27 @@ def main():
             plan.run(sv)
         ms = timed(run, a.launches) - timed(lambda: sv.init_basis(0), a.launches)
         print(f"tile pass complex64 (one CZ): {ms:.3f} ms, {2 * 8 * 2**a.n / ms / 1e6:.0f} GB/s", flush=True)
+        return
+    if a.kernel == "blocks":
+        # one complex64 tile pass (13-qubit tiles) holding `blocks` random
+        # k-qubit unitaries on overlapping windows of the tile qubits (so
+        # that none fuse): the block kernel's cost in isolation
+        import numpy as np
+        rng = np.random.Generator(np.random.PCG64(17))
+        gates = []
+        for i in range(a.blocks):
+            z = rng.standard_normal((2 ** a.k, 2 ** a.k)) + 1j * rng.standard_normal((2 ** a.k, 2 ** a.k))
+            q, r = np.linalg.qr(z)
+            lo = i % (13 - a.k + 1)
+            gates.append(Gate("unitary", tuple(range(lo, lo + a.k)), (), (), -1, q))
+        sv = qvm.StateVector(a.n, "c64", init=0)
+        plan = qvm.Plan(gates, a.n, "c64", k_max=a.k, tile_qubits=13)
+        assert plan.stats()["passes"] == 1 and plan.stats()["blocks"] == a.blocks
+        for _ in range(a.launches):
+            sv.init_basis(0)
+            plan.run(sv)
+        torch.cuda.synchronize()
+        print(f"blocks k={a.k} x {a.blocks} n={a.n} x {a.launches}", flush=True)
         return
     if a.kernel == "copy":
         real = torch.float32 if a.dtype == "c64" else torch.float64

@@ -22,7 +22,7 @@ def _gpu(require_gpu):
 
 def test_collect_train_choose(tmp_path):
     path = str(tmp_path / "rows.npz")
-    rows = lp.collect(0, 40, path, n_range=(13, 16), g_range=(60, 120))
+    rows = lp.collect(0, 40, path, n_range=(13, 16), g_range=(60, 120), mix=False)
     assert rows > 40
     F, T = lp.load_rows(path)
     assert F.shape[1] == lp.NFEAT and np.all(T > 0)

@@ -183,6 +183,36 @@ def random_planner_circuit(seed: int, n_range=(26, 32), g_range=(100, 500),
     return nn, gates
 
 
+PLANNER_FAMILIES = ("random", "random_long", "layered", "qft", "rotation_cnot")
+
+
+def planner_mix_circuit(seed: int):
+    """Training circuits for the cost model: a seeded mixture of circuit
+    families so that pass shapes cover what users run, not only the random
+    gate soup.  Family (by seed): random 100-500 gates (45%), random
+    500-1,500 gates (15%), U3 + CZ brick of depth 4-40 (20%), QFT followed
+    by a brick of depth 0-20 (10%), rotation + cyclic CNOT layers, 2-12 of
+    them (10%); n ~ U{26..32} for the short random circuits and U{26..30}
+    for the others (their passes are long; the qubit count is a feature, so
+    the model still sees its scaling).  Returns (n, gates, family)."""
+    rng = _rng(seed)
+    u = rng.random()
+    sub = int(rng.integers(0, 2 ** 31))
+    if u < 0.45:
+        n, gates = random_planner_circuit(sub)
+        return n, gates, "random"
+    if u < 0.60:
+        n, gates = random_planner_circuit(sub, n_range=(26, 30), g_range=(500, 1500))
+        return n, gates, "random_long"
+    n = int(rng.integers(26, 31))
+    if u < 0.80:
+        return n, layered_u3_cz(n, int(rng.integers(4, 41)), sub), "layered"
+    if u < 0.90:
+        gates = qft_circuit(n) + layered_u3_cz(n, int(rng.integers(0, 21)), sub)
+        return n, gates, "qft"
+    return n, rotation_cnot_circuit(n, int(rng.integers(2, 13)), sub), "rotation_cnot"
+
+
 def _random_unitary(rng, dim):
     z = rng.standard_normal((dim, dim)) + 1j * rng.standard_normal((dim, dim))
     q, r = np.linalg.qr(z)
