@@ -20,6 +20,7 @@ CZ, Toffoli}, layered U3 + CZ bricks, QFT prefixes, rotation + CNOT layers;
     python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 2000 --out D.npz
     python -m paper_2212_14201_amd.learned_planner train    --data D.npz --model M.npz
     python -m paper_2212_14201_amd.learned_planner evaluate --model M.npz --first 100000 --count 200
+    python -m paper_2212_14201_amd.learned_planner explain  --model M.npz --workload qft30
 """
 from __future__ import annotations
 
@@ -362,9 +363,26 @@ def summarize(recs, checks):
     return out
 
 
+def explain(planner, n, gates, x=0, dtype="c64", measure=True):
+    """Every candidate's predicted (and, if `measure`, measured) time for one
+    circuit; returns (choice, rows)."""
+    ga = qvm.GateArray(gates)
+    cand, _, pred = planner.choose(ga, n, dtype)
+    rows = []
+    sv = qvm.StateVector(n, dtype, init=0) if measure else None
+    for c in CANDIDATES:
+        p = build_plan(ga, n, dtype, c)
+        if p is None:
+            continue
+        rows.append({"candidate": "%s-%d-%d" % c, "predicted_ms": planner.predict_plan_ms(p),
+                     "measured_ms": time_plan(sv, p, x)[0] if measure else None})
+    return {"choice": "%s-%d-%d" % cand, "predicted_ms": pred}, rows
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["collect", "train", "evaluate"])
+    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "explain"])
+    ap.add_argument("--workload", default="qft30", help="explain: a named workload of workloads.config_circuit")
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--out", default="gpurun_out/planner_train.npz")
@@ -384,6 +402,13 @@ def main():
         planner, hist = train(F, T, epochs=a.epochs)
         planner.save(a.model)
         print(json.dumps({"rows": len(F), "final_loss": hist[-1]}), flush=True)
+    elif a.cmd == "explain":
+        from workloads import config_circuit
+        cfg = config_circuit(a.workload)
+        choice, rows = explain(LearnedPlanner.load(a.model), cfg["n"], cfg["gates"], cfg["init"])
+        print(json.dumps(choice), flush=True)
+        for r in rows:
+            print(json.dumps(r), flush=True)
     else:
         planner = LearnedPlanner.load(a.model)
         recs, checks = evaluate(planner, a.first, a.count, all_cands=a.all_cands, mix=a.mix)
