@@ -228,6 +228,56 @@ std::vector<Unit> fuse(const std::vector<PGate>& G, const std::vector<int>& subs
     return out;
 }
 
+// Standalone diagonal units whose qubits all lie inside an adjacent block
+// are multiplied into that block: into the block before them when that block
+// is the last unit touching any of their qubits, else into the block after
+// them when that block is the next unit touching any of them.  The block
+// matrix absorbs the phases for free, and per-qubit gate order is kept
+// (nothing else acts on those qubits in between).
+void absorb_diagonals(std::vector<Unit>& units, const std::vector<PGate>& G) {
+    auto qmask_of = [&](const Unit& u) {
+        uint64_t m = 0;
+        if (u.block)
+            for (int q : u.qubits) m |= 1ull << q;
+        else
+            for (int gi : u.gates) m |= G[gi].qmask;
+        return m;
+    };
+    auto inside = [&](const Unit& b, uint64_t m) { return b.block && (m & ~qmask_of(b)) == 0; };
+    std::vector<char> gone(units.size(), 0);
+    // into the block before
+    for (size_t i = 0; i < units.size(); ++i) {
+        if (units[i].block) continue;
+        const uint64_t m = qmask_of(units[i]);
+        for (size_t j = i; j-- > 0;) {
+            if (gone[j] || (qmask_of(units[j]) & m) == 0) continue;
+            if (inside(units[j], m)) {
+                for (int gi : units[i].gates) units[j].gates.push_back(gi);
+                gone[i] = 1;
+            }
+            break;
+        }
+    }
+    // into the block after
+    for (size_t i = units.size(); i-- > 0;) {
+        if (gone[i] || units[i].block) continue;
+        const uint64_t m = qmask_of(units[i]);
+        for (size_t j = i + 1; j < units.size(); ++j) {
+            if (gone[j] || (qmask_of(units[j]) & m) == 0) continue;
+            if (inside(units[j], m)) {
+                units[j].gates.insert(units[j].gates.begin(), units[i].gates.begin(), units[i].gates.end());
+                gone[i] = 1;
+            }
+            break;
+        }
+    }
+    std::vector<Unit> kept;
+    kept.reserve(units.size());
+    for (size_t i = 0; i < units.size(); ++i)
+        if (!gone[i]) kept.push_back(std::move(units[i]));
+    units.swap(kept);
+}
+
 struct Builder {
     int n;
     qvm_dtype dt;
@@ -419,6 +469,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 }
     } else if (tile_qubits == 0) {
         units = fuse(G, all, n, k_max, ~0ull);
+        absorb_diagonals(units, G);
     }
     const bool tile_mode = !partition && tile_qubits != 0;
     size_t next_unit = 0;
@@ -486,6 +537,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 T |= 1ull << w.second;
             }
             pp.units = fuse(G, taken, n, k_max, T);
+            absorb_diagonals(pp.units, G);
         } else {
             // diagonal units ride in the pass of the next block
             while (next_unit < units.size()) {
