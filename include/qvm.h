@@ -222,6 +222,17 @@ qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits,
                            int k_max, int tile_qubits, qvm_dtype dt,
                            qvm_plan** out);
 
+/* qvm_plan_greedy with options.  QVM_PLAN_NO_IMAGE builds the plan for
+ * scoring only: schedule, statistics, blocks' qubits and gates and the pass
+ * features are filled in, but no block matrices and no device image (the
+ * expensive part), so qvm_run_plan and a block's matrix return QVM_ESTATE.
+ * The learned planner scores candidates this way and builds only the chosen
+ * one in full.  QVM_EARG for unknown flags. */
+#define QVM_PLAN_NO_IMAGE 1u
+qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubits,
+                              int k_max, int tile_qubits, qvm_dtype dt, uint32_t flags,
+                              qvm_plan** out);
+
 /* Plan from an explicit partition: block_of_gate[i] is the block id of gate
  * i; blocks run in ascending id order, one pass each.  QVM_EARG if a block
  * spans more than k_max qubits or the partition breaks the per-qubit gate

@@ -86,6 +86,7 @@ struct qvm_plan {
     int n_diag_ops;
     uint64_t id;
     uint64_t pass_table;                    // offset of the PassDesc table in the blob
+    bool image;                             // false: built for scoring only (no matrices, no image)
 };
 
 namespace qvm {
@@ -109,9 +110,16 @@ void apply_small(std::vector<cd>& v, int k_reg, const cd* u, int k, const int* p
             in[j] = v[o];
         }
         for (int i = 0; i < dim; ++i) {
-            cd s = 0;
-            for (int j = 0; j < dim; ++j) s += u[i * dim + j] * in[j];
-            v[idx[i]] = s;
+            // plain real arithmetic (finite operands; std::complex's product
+            // would call the library's NaN-recovering routine per term)
+            double sr = 0, si = 0;
+            for (int j = 0; j < dim; ++j) {
+                const double ar = u[i * dim + j].real(), ai = u[i * dim + j].imag();
+                const double br = in[j].real(), bi = in[j].imag();
+                sr += ar * br - ai * bi;
+                si += ar * bi + ai * br;
+            }
+            v[idx[i]] = cd(sr, si);
         }
     }
 }
@@ -124,19 +132,21 @@ std::vector<cd> block_matrix(const std::vector<PGate>& G, const std::vector<int>
     std::vector<cd> M((size_t)dim * dim, cd(0, 0));
     std::map<int, int> pos;
     for (int r = 0; r < k; ++r) pos[qubits[r]] = r;
+    // each gate's targets and controls in block bit positions, once
+    struct Placed { const PGate* g; int p[QVM_MAX_K]; uint64_t cm; };
+    std::vector<Placed> pl(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) {
+        const PGate& g = G[gates[i]];
+        pl[i].g = &g;
+        for (int r = 0; r < g.k; ++r) pl[i].p[r] = pos.at(g.t[r]);
+        pl[i].cm = 0;
+        for (uint64_t m = g.cmask; m; m &= m - 1) pl[i].cm |= 1ull << pos.at(__builtin_ctzll(m));
+    }
     std::vector<cd> col(dim);
     for (int c = 0; c < dim; ++c) {
         std::fill(col.begin(), col.end(), cd(0, 0));
         col[c] = 1.0;
-        for (int gi : gates) {
-            const PGate& g = G[gi];
-            int p[QVM_MAX_K];
-            for (int r = 0; r < g.k; ++r) p[r] = pos.at(g.t[r]);
-            uint64_t cm = 0;
-            for (int q = 0; q < 64; ++q)
-                if ((g.cmask >> q) & 1) cm |= 1ull << pos.at(q);
-            apply_small(col, k, g.u.data(), g.k, p, cm);
-        }
+        for (const Placed& x : pl) apply_small(col, k, x.g->u.data(), x.g->k, x.p, x.cm);
         for (int r = 0; r < dim; ++r) M[(size_t)r * dim + c] = col[r];
     }
     return M;
@@ -375,7 +385,7 @@ std::vector<R> fragments(const std::vector<cd>& M, int k) {
 }  // namespace
 
 qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int k_max,
-                      int tile_qubits, const uint32_t* partition, qvm_plan** out) {
+                      int tile_qubits, const uint32_t* partition, qvm_plan** out, bool image) {
     if (!out) return fail(QVM_EARG, "NULL out");
     *out = nullptr;
     if (n < 1 || n > QVM_MAX_QUBITS) return fail(QVM_EARG, "n_qubits outside 1..34");
@@ -483,6 +493,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
     P->tile_qubits = tile_qubits;
     P->n_diag_ops = 0;
     P->id = g_plan_ids.fetch_add(1);
+    P->image = image;
     P->block_of_gate.assign(ng, 0xffffffffu);
     P->exec_pos.assign(ng, -1);
     P->unit_of.assign(ng, -1);
@@ -599,20 +610,21 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                     if (std::find(bq.begin(), bq.end(), w) == bq.end()) bq.push_back(w);
                 }
                 const int k = (int)bq.size();
-                std::vector<cd> M = block_matrix(G, u.gates, bq);
+                std::vector<cd> M;
                 op.type = TOP_BLOCK;
                 op.k = k;
                 for (int r = 0; r < k; ++r) op.lb[r] = local_of_wire[bq[r]];
-                {
+                if (image) {
+                    M = block_matrix(G, u.gates, bq);
                     const std::vector<uint32_t> tab = block_table(op.lb, k, L, dt);
                     op.tab = B.put(tab.data(), tab.size() * sizeof(uint32_t));
-                }
-                if (dt == QVM_C64) {
-                    auto f = fragments<float>(M, k);
-                    op.data = B.put(f.data(), f.size() * sizeof(float));
-                } else {
-                    auto f = fragments<double>(M, k);
-                    op.data = B.put(f.data(), f.size() * sizeof(double));
+                    if (dt == QVM_C64) {
+                        auto f = fragments<float>(M, k);
+                        op.data = B.put(f.data(), f.size() * sizeof(float));
+                    } else {
+                        auto f = fragments<double>(M, k);
+                        op.data = B.put(f.data(), f.size() * sizeof(double));
+                    }
                 }
                 qvm_plan::Block blk;
                 blk.qubits = bq;
@@ -857,13 +869,20 @@ extern "C" {
 
 qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits, int k_max,
                            int tile_qubits, qvm_dtype dt, qvm_plan** out) {
-    return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out);
+    return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out, true);
+}
+
+qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubits, int k_max,
+                              int tile_qubits, qvm_dtype dt, uint32_t flags, qvm_plan** out) {
+    if (flags & ~(uint32_t)QVM_PLAN_NO_IMAGE) return fail(QVM_EARG, "unknown plan flags");
+    return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out,
+                      (flags & QVM_PLAN_NO_IMAGE) == 0);
 }
 
 qvm_status qvm_plan_from_partition(const qvm_gate* gates, size_t n_gates, const uint32_t* block_of_gate,
                                    int n_qubits, int k_max, qvm_dtype dt, qvm_plan** out) {
     if (n_gates && !block_of_gate) return fail(QVM_EARG, "NULL partition");
-    return build_plan(gates, n_gates, n_qubits, dt, k_max, 0, block_of_gate, out);
+    return build_plan(gates, n_gates, n_qubits, dt, k_max, 0, block_of_gate, out, true);
 }
 
 qvm_status qvm_plan_pass_features(const qvm_plan* p, float* out, size_t cap, int32_t* n_passes) {
@@ -919,6 +938,7 @@ qvm_status qvm_plan_block(const qvm_plan* p, int32_t i, int32_t* k, int32_t* k_t
     if (gate_idx)
         for (size_t r = 0; r < b.gates.size(); ++r) gate_idx[r] = b.gates[r];
     if (pass) *pass = b.pass;
+    if (m_out && !p->image) return fail(QVM_ESTATE, "plan was built for scoring only (QVM_PLAN_NO_IMAGE)");
     if (m_out)
         for (size_t r = 0; r < b.m.size(); ++r) {
             m_out[2 * r] = b.m[r].real();
@@ -945,6 +965,7 @@ qvm_status qvm_plan_final_layout(const qvm_plan* p, int32_t* perm_out) {
 qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* p) {
     if (!sv || !p) return fail(QVM_EARG, "NULL argument");
     if (sv->failed) return fail(QVM_ESTATE, "state handle failed earlier");
+    if (!p->image) return fail(QVM_ESTATE, "plan was built for scoring only (QVM_PLAN_NO_IMAGE)");
     if (p->n != sv->n || p->dt != sv->dt) return fail(QVM_EARG, "plan built for another n or dtype");
     return run_plan(sv, p);
 }

@@ -64,10 +64,10 @@ def cand_for_dtype(c, dtype):
     return mode, k, tile
 
 
-def build_plan(ga, n, dtype, cand):
+def build_plan(ga, n, dtype, cand, image=True):
     mode, k, tile = cand_for_dtype(cand, dtype)
     try:
-        return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile)
+        return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile, image=image)
     except qvm.QvmError:
         return None        # e.g. a Toffoli does not fit 2-qubit blocks
 
@@ -198,25 +198,27 @@ class LearnedPlanner:
     def choose(self, ga, n, dtype="c64"):
         """Returns (candidate, plan, predicted ms) with the smallest prediction.
 
-        The candidate plans are built on host threads (the library's planner
-        is reentrant and ctypes releases the GIL) and all their passes are
-        scored in one MLP forward."""
+        The candidates are planned for scoring only (no block matrices or
+        device image) on host threads (the library's planner is reentrant and
+        ctypes releases the GIL), all their passes are scored in one MLP
+        forward, and only the winner is then built in full."""
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max_workers=min(len(CANDIDATES), os.cpu_count() or 1)) as ex:
-            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c), CANDIDATES))
+            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), CANDIDATES))
         live = [(c, p) for c, p in zip(CANDIDATES, plans) if p is not None]
         feats = [plan_features(p) for _, p in live]
         rows = np.concatenate(feats)
         if len(rows) == 0:                   # nothing to run: every plan is empty
-            return live[0][0], live[0][1], 0.0
-        ms = self.predict_pass_ms(rows)
-        best, o = None, 0
-        for (c, p), f in zip(live, feats):
-            pred = float(ms[o:o + len(f)].sum())
-            o += len(f)
-            if best is None or pred < best[2]:
-                best = (c, p, pred)
-        return best
+            best = (live[0][0], 0.0)
+        else:
+            ms = self.predict_pass_ms(rows)
+            best, o = None, 0
+            for (c, _), f in zip(live, feats):
+                pred = float(ms[o:o + len(f)].sum())
+                o += len(f)
+                if best is None or pred < best[1]:
+                    best = (c, pred)
+        return best[0], build_plan(ga, n, dtype, best[0]), best[1]
 
     def save(self, path):
         extra = {"mu": self.mu, "sd": self.sd}

@@ -344,6 +344,8 @@ def _declare_plan(L):
     sig = {
         "qvm_plan_greedy": (st, [_gp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.POINTER(_vp)]),
+        "qvm_plan_greedy_ex": (st, [_gp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_vp)]),
         "qvm_plan_from_partition": (st, [_gp, ctypes.c_size_t, _u32p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.POINTER(_vp)]),
         "qvm_plan_info": (st, [_vp, ctypes.POINTER(QvmPlanStats)]),
@@ -359,19 +361,29 @@ def _declare_plan(L):
         f.argtypes = args
 
 
+QVM_PLAN_NO_IMAGE = 1
+
+
 class Plan:
-    """A fused execution plan (host object built by the library)."""
+    """A fused execution plan (host object built by the library).
+
+    image=False builds it for scoring only (schedule, statistics and pass
+    features without block matrices or device image); such a plan cannot run."""
 
     def __init__(self, gates, n: int, dtype: str = "c64", k_max: int = 5, tile_qubits: int = 0,
-                 partition=None):
+                 partition=None, image: bool = True):
         _declare_plan(lib())
         self.gates = gates if isinstance(gates, GateArray) else GateArray(gates)
         self.n = int(n)
         self.dtype = "c64" if _dt(dtype) == QVM_C64 else "c128"
+        self.k_max, self.tile_qubits, self.image = int(k_max), int(tile_qubits), bool(image)
         h = _vp()
         if partition is None:
-            check(lib().qvm_plan_greedy(self.gates.ptr(), self.gates.n, self.n, int(k_max),
-                                        int(tile_qubits), _dt(dtype), ctypes.byref(h)))
+            flags = 0 if image else QVM_PLAN_NO_IMAGE
+            check(lib().qvm_plan_greedy_ex(self.gates.ptr(), self.gates.n, self.n, int(k_max),
+                                           int(tile_qubits), _dt(dtype), flags, ctypes.byref(h)))
+        elif not image:
+            raise ValueError("scoring-only plans are built by the greedy planner only")
         else:
             part = np.ascontiguousarray(partition, dtype=np.uint32)
             check(lib().qvm_plan_from_partition(self.gates.ptr(), self.gates.n,

@@ -157,3 +157,35 @@ def test_sweep_gate_lists():
                 u = np.asarray(g.matrix)
                 assert np.allclose(u @ u.conj().T, np.eye(u.shape[0]), atol=1e-12)
     assert sweeps.touched_fraction("toffoli") == 0.25
+
+
+def test_scoring_only_plans_match_full_plans():
+    """A plan built without its image carries the same schedule, statistics
+    (apart from the device bytes) and pass features as the full plan, and
+    refuses to hand out block matrices."""
+    lp = pytest.importorskip("paper_2212_14201_amd.learned_planner")
+    cfg = config_circuit("qft30")
+    for k, tile in ((5, 0), (3, 13), (4, 12)):
+        full = qvm.Plan(cfg["gates"], 30, "c64", k_max=k, tile_qubits=tile)
+        lean = qvm.Plan(cfg["gates"], 30, "c64", k_max=k, tile_qubits=tile, image=False)
+        sf, sl = full.stats(), lean.stats()
+        assert sl["device_bytes"] < sf["device_bytes"]
+        sf.pop("device_bytes"), sl.pop("device_bytes")
+        assert sf == sl
+        assert np.array_equal(lp.plan_features(full), lp.plan_features(lean))
+        for a, b in zip(full.schedule(), lean.schedule()):
+            assert np.array_equal(a, b)
+        assert np.array_equal(full.final_layout(), lean.final_layout())
+        with pytest.raises(qvm.QvmError):
+            lean.block(0)
+    with pytest.raises(ValueError):
+        qvm.Plan(cfg["gates"], 30, "c64", k_max=2, partition=np.zeros(len(cfg["gates"])), image=False)
+
+
+def test_plan_flags_rejected():
+    qvm.Plan([Gate("h", (0,))], 3, "c64", k_max=3)
+    L = qvm.lib()
+    ga = qvm.GateArray([Gate("h", (0,))])
+    h = qvm.ctypes.c_void_p()
+    st = L.qvm_plan_greedy_ex(ga.ptr(), ga.n, 3, 3, 0, qvm.QVM_C64, 2, qvm.ctypes.byref(h))
+    assert qvm.STATUS[st] == "QVM_EARG" and not h.value
