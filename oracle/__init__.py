@@ -256,11 +256,22 @@ def block_matrix(gates, block_qubits) -> np.ndarray:
     return M
 
 
+def is_diagonal(gate) -> bool:
+    """True when the gate's target matrix has zeros off its diagonal (then,
+    controls included, the gate is diagonal in the computational basis)."""
+    u = gate_matrix(gate)
+    return not np.any(u - np.diag(np.diag(u)))
+
+
 def validate_plan(gates, blocks, k_max: int):
     """A plan is a list of blocks, each a list of gate indices, in execution
     order.  Valid iff every gate is in exactly one block, every block spans
-    at most k_max qubits, and for every qubit the gates touching it are
-    executed in program order.  Returns (ok, reason)."""
+    at most k_max qubits, and the execution order respects the dependency
+    graph of the circuit: two gates that share a qubit keep their program
+    order unless both are diagonal (diagonal matrices commute).  Per qubit:
+    a non-diagonal gate runs after every earlier gate on that qubit, a
+    diagonal gate after the last earlier non-diagonal one.  Returns
+    (ok, reason)."""
     seen = {}
     for b, blk in enumerate(blocks):
         qs = set()
@@ -273,17 +284,27 @@ def validate_plan(gates, blocks, k_max: int):
             return False, f"block {b} spans {len(qs)} > {k_max} qubits"
     if len(seen) != len(gates):
         return False, "not every gate is in a block"
-    # per-qubit order: position of each gate in execution order
+    # position of each gate in execution order
     order = {}
     t = 0
     for blk in blocks:
         for gi in blk:
             order[gi] = t
             t += 1
-    last = {}
+    diag = [is_diagonal(g) for g in gates]
+    last_nd = {}        # qubit -> last non-diagonal gate on it
+    since = {}          # qubit -> diagonal gates on it after that one
     for gi, g in enumerate(gates):
         for q in g.qubits():
-            if q in last and order[last[q]] > order[gi]:
-                return False, f"gates {last[q]} and {gi} on qubit {q} out of order"
-            last[q] = gi
+            before = [last_nd[q]] if q in last_nd else []
+            if not diag[gi]:
+                before += since.get(q, [])
+            for p in before:
+                if order[p] > order[gi]:
+                    return False, f"gates {p} and {gi} on qubit {q} out of order"
+            if diag[gi]:
+                since.setdefault(q, []).append(gi)
+            else:
+                last_nd[q] = gi
+                since[q] = []
     return True, ""

@@ -361,6 +361,39 @@ def test_plan_validator():
     assert not oracle.validate_plan(gates, [[3], [0, 1, 2]], 3)[0]      # z before h on qubit 2
 
 
+def test_plan_validator_diagonal_commutation():
+    """Diagonal gates may trade places between the same non-diagonal gates;
+    every order the validator accepts gives the program-order state (brute
+    force over random orders of small circuits rich in diagonal gates)."""
+    g = [Gate("h", (0,)), Gate("z", (1,), (0,)), Gate("rz", (1,), (), (0.4,)), Gate("t", (0,)),
+         Gate("x", (1,))]
+    assert oracle.validate_plan(g, [[0], [3], [2], [1], [4]], 2)[0]
+    assert not oracle.validate_plan(g, [[0], [1], [4], [2], [3]], 2)[0]   # x(1) before rz(1)
+    assert not oracle.validate_plan(g, [[3], [0], [1], [2], [4]], 2)[0]   # t(0) before h(0)
+    assert not oracle.validate_plan(g, [[0], [4], [1], [2], [3]], 2)[0]   # x(1) before cz
+    n = 4
+    rng = np.random.default_rng(11)
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    accepted = 0
+    for trial in range(30):
+        gates = []
+        for _ in range(9):
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            kind = int(rng.integers(0, 6))
+            gates.append([Gate("h", (a,)), Gate("z", (a,), (b,)), Gate("rz", (a,), (), (float(rng.uniform(0, 6)),)),
+                          Gate("p", (a,), (b,), (float(rng.uniform(0, 6)),)), Gate("rzz", (a, b), (), (0.7,)),
+                          Gate("x", (a,), (b,))][kind])
+        want = oracle.apply_gates(psi.copy(), n, gates)
+        for _ in range(40):
+            perm = [int(v) for v in rng.permutation(len(gates))]
+            if not oracle.validate_plan(gates, [[i] for i in perm], n)[0]:
+                continue
+            accepted += perm != sorted(perm)
+            got = oracle.apply_gates(psi.copy(), n, [gates[i] for i in perm])
+            assert np.max(np.abs(got - want)) < 1e-12
+    assert accepted >= 10
+
+
 # ------------------------------------------------------------- cost-model MLP
 def test_mlp_backward_matches_central_differences():
     from oracle import mlp
