@@ -209,6 +209,13 @@ std::vector<Unit> fuse(const std::vector<PGate>& G, const std::vector<int>& subs
                 if (!cur.gates.empty() && (g.qmask & ~S) == 0) {
                     cur.gates.push_back(gi);
                     take = true;
+                } else if (!cur.gates.empty() && (g.qmask & S) != 0 && (g.qmask & ~allowed) == 0 &&
+                           popc(S | g.qmask) <= std::min(3, k_max)) {
+                    // widening the block up to the 3 qubits it is padded to
+                    // anyway costs nothing
+                    cur.gates.push_back(gi);
+                    S |= g.qmask;
+                    take = true;
                 } else if ((g.qmask & S) == 0) {
                     out.push_back(Unit{false, {gi}, {}});
                     take = true;
@@ -238,13 +245,17 @@ std::vector<Unit> fuse(const std::vector<PGate>& G, const std::vector<int>& subs
     return out;
 }
 
-// Standalone diagonal units whose qubits all lie inside an adjacent block
-// are multiplied into that block: into the block before them when that block
-// is the last unit touching any of their qubits, else into the block after
-// them when that block is the next unit touching any of them.  The block
-// matrix absorbs the phases for free, and per-qubit gate order is kept
-// (nothing else acts on those qubits in between).
-void absorb_diagonals(std::vector<Unit>& units, const std::vector<PGate>& G) {
+// Standalone diagonal units are multiplied into a neighbouring block: into
+// the last block before them that touches any of their qubits, else into the
+// first block after them that does (diagonal units in between are passed
+// over: diagonal gates commute).  The block must cover the unit's qubits or
+// be narrower than the 3 qubits every block is padded to anyway, in which case
+// it grows by the unit's qubits (at most min(3, k_max), within `allowed`).
+// The block matrix takes the phases for free, and per-qubit order is kept up
+// to commuting diagonal gates.
+void absorb_diagonals(std::vector<Unit>& units, const std::vector<PGate>& G, int k_max,
+                      uint64_t allowed) {
+    const int grow_to = std::min(3, k_max);
     auto qmask_of = [&](const Unit& u) {
         uint64_t m = 0;
         if (u.block)
@@ -253,15 +264,21 @@ void absorb_diagonals(std::vector<Unit>& units, const std::vector<PGate>& G) {
             for (int gi : u.gates) m |= G[gi].qmask;
         return m;
     };
-    auto inside = [&](const Unit& b, uint64_t m) { return b.block && (m & ~qmask_of(b)) == 0; };
+    auto take = [&](Unit& b, uint64_t m) {
+        const uint64_t bm = qmask_of(b);
+        if ((m & ~bm) == 0) return true;
+        if ((m & ~allowed) != 0 || popc(bm | m) > grow_to) return false;
+        for (uint64_t x = m & ~bm; x; x &= x - 1) b.qubits.push_back(__builtin_ctzll(x));
+        return true;
+    };
     std::vector<char> gone(units.size(), 0);
     // into the block before
     for (size_t i = 0; i < units.size(); ++i) {
         if (units[i].block) continue;
         const uint64_t m = qmask_of(units[i]);
         for (size_t j = i; j-- > 0;) {
-            if (gone[j] || (qmask_of(units[j]) & m) == 0) continue;
-            if (inside(units[j], m)) {
+            if (gone[j] || !units[j].block || (qmask_of(units[j]) & m) == 0) continue;
+            if (take(units[j], m)) {
                 for (int gi : units[i].gates) units[j].gates.push_back(gi);
                 gone[i] = 1;
             }
@@ -273,8 +290,8 @@ void absorb_diagonals(std::vector<Unit>& units, const std::vector<PGate>& G) {
         if (gone[i] || units[i].block) continue;
         const uint64_t m = qmask_of(units[i]);
         for (size_t j = i + 1; j < units.size(); ++j) {
-            if (gone[j] || (qmask_of(units[j]) & m) == 0) continue;
-            if (inside(units[j], m)) {
+            if (gone[j] || !units[j].block || (qmask_of(units[j]) & m) == 0) continue;
+            if (take(units[j], m)) {
                 units[j].gates.insert(units[j].gates.begin(), units[i].gates.begin(), units[i].gates.end());
                 gone[i] = 1;
             }
@@ -304,7 +321,7 @@ struct Builder {
 };
 
 // Runs of at least this many terms take the angle-accumulating path of the
-// tile kernel (one integer add per term and element, then one complex factor
+// tile kernel (one integer add per term and thread, then one complex factor
 // per element); shorter runs multiply term by term.  Sign-only runs end in a
 // sign flip instead of a factor, so they pay off sooner.
 constexpr int kTurnsMinTerms = 8;
@@ -318,6 +335,44 @@ uint64_t turns_of(cd v) {
     const double s = std::ldexp(a, 64);
     if (!(s < 18446744073709551616.0)) return 0;                    // rounded up to a full turn
     return (uint64_t)std::nearbyint(s);
+}
+
+// Angle-path terms of a long diagonal run (layout in tile.hpp): each term's
+// angle in the kernel's fixed-point width; a condition h = 0 on an element
+// bit h becomes 1 - h, so a term splits into +-angle on the supersets of its
+// required ones; terms with equal conditions in a group are merged (sums
+// modulo a full turn are exact) and zero sums dropped.  off gets 2^h + 1
+// group offsets.
+void angle_terms(const std::vector<DSub>& run, int L, qvm_dtype dt, std::vector<DTerm>& terms,
+                 std::vector<uint32_t>& off) {
+    const int nhb = L > kLogTileThreads ? L - kLogTileThreads : 0;
+    const uint32_t ne = 1u << nhb, tm = kTileThreads - 1;
+    const uint64_t wmask = dt == QVM_C64 ? 0xffffffffull : ~0ull;
+    std::vector<std::vector<DTerm>> grp(ne);
+    for (const DSub& d : run) {
+        const uint64_t w = dt == QVM_C64 ? (d.turns + (1ull << 31)) >> 32 : d.turns;
+        const uint32_t mh = (d.lmask >> kLogTileThreads) & (ne - 1);
+        const uint32_t vh = (d.lval >> kLogTileThreads) & (ne - 1);
+        const uint32_t ones = mh & vh, zeros = mh & ~vh;
+        for (uint32_t T = zeros;; T = (T - 1) & zeros) {
+            const uint64_t v = (__builtin_popcount(T) & 1 ? 0 - w : w) & wmask;
+            std::vector<DTerm>& g = grp[ones | T];
+            auto same = std::find_if(g.begin(), g.end(), [&](const DTerm& e) {
+                return e.omask == d.omask && e.oval == d.oval && e.lmask == (d.lmask & tm) &&
+                       e.lval == (d.lval & tm);
+            });
+            if (same != g.end()) same->turns = (same->turns + v) & wmask;
+            else g.push_back(DTerm{d.omask, d.oval, v, d.lmask & tm, d.lval & tm});
+            if (T == 0) break;
+        }
+    }
+    terms.clear();
+    off.assign(ne + 1, 0);
+    for (uint32_t g = 0; g < ne; ++g) {
+        for (const DTerm& e : grp[g])
+            if (e.turns) terms.push_back(e);
+        off[g + 1] = (uint32_t)terms.size();
+    }
 }
 
 // Address table of a block op (layout in tile.hpp): the wave-uniform parts
@@ -479,7 +534,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 }
     } else if (tile_qubits == 0) {
         units = fuse(G, all, n, k_max, ~0ull);
-        absorb_diagonals(units, G);
+        absorb_diagonals(units, G, k_max, ~0ull);
     }
     const bool tile_mode = !partition && tile_qubits != 0;
     size_t next_unit = 0;
@@ -548,7 +603,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 T |= 1ull << w.second;
             }
             pp.units = fuse(G, taken, n, k_max, T);
-            absorb_diagonals(pp.units, G);
+            absorb_diagonals(pp.units, G, k_max, T);
         } else {
             // diagonal units ride in the pass of the next block
             while (next_unit < units.size()) {
@@ -579,30 +634,55 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         const int pi = (int)P->passes.size();
         std::vector<TOp> ops;
         std::vector<DSub> run;
-        auto flush = [&]() {
-            if (run.empty()) return;
-            TOp op{};
-            op.type = TOP_DIAGRUN;
-            op.k = (int32_t)run.size();
-            op.data = B.put(run.data(), run.size() * sizeof(DSub));
-            // long runs accumulate angles (one add per term and element, one
-            // factor per element); short ones multiply term by term
-            bool signs = true;
-            for (const DSub& d : run) signs = signs && d.neg;
-            const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
-            op.flags = (int)run.size() >= at_least ? DRUN_TURNS | (signs ? DRUN_SIGNS : 0) : 0;
-            ops.push_back(op);
-            run.clear();
-        };
-        for (auto& u : pp.units) {
-            TOp op{};
+        // Diagonal gates commute with each other and with blocks on other
+        // wires, so they are held back until a block touches one of their
+        // wires (or the pass ends) and then emitted as one run: fewer, longer
+        // runs.  Their schedule positions are given when they are emitted.
+        std::vector<const Unit*> held;
+        uint64_t held_wires = 0;
+        auto place = [&](const Unit& u) {
             for (int gi : u.gates) {
                 P->exec_pos[G[gi].src] = exec_counter++;
                 P->unit_of[G[gi].src] = unit_counter;
             }
             ++unit_counter;
+        };
+        auto flush = [&]() {
+            for (const Unit* h : held) place(*h);
+            held.clear();
+            held_wires = 0;
+            if (run.empty()) return;
+            TOp op{};
+            op.type = TOP_DIAGRUN;
+            // long runs accumulate angles (one add per term and thread, one
+            // factor per element); short ones multiply term by term
+            bool signs = true;
+            for (const DSub& d : run) signs = signs && d.neg;
+            const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
+            if ((int)run.size() >= at_least) {
+                std::vector<DTerm> terms;
+                std::vector<uint32_t> off;
+                angle_terms(run, L, dt, terms, off);
+                run.clear();
+                if (terms.empty()) return;          // the run's phases cancel
+                op.k = (int32_t)terms.size();
+                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0);
+                op.data = B.put(terms.data(), terms.size() * sizeof(DTerm));
+                op.tab = B.put(off.data(), off.size() * sizeof(uint32_t));
+            } else {
+                op.k = (int32_t)run.size();
+                op.data = B.put(run.data(), run.size() * sizeof(DSub));
+                run.clear();
+            }
+            ops.push_back(op);
+        };
+        for (auto& u : pp.units) {
+            TOp op{};
             if (u.block) {
-                flush();
+                uint64_t bw = 0;
+                for (int w : u.qubits) bw |= 1ull << w;
+                if (held_wires & bw) flush();
+                place(u);
                 std::vector<int> bq = u.qubits;
                 const int k_true = (int)bq.size();
                 for (int i = 0; (int)bq.size() < 3 && i < L; ++i) {
@@ -639,6 +719,8 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             } else {
                 // diagonal gate -> phase terms over its target patterns
                 const PGate& g = G[u.gates[0]];
+                held.push_back(&u);
+                held_wires |= g.qmask;
                 uint64_t tmask = 0;
                 for (int r = 0; r < g.k; ++r) tmask |= 1ull << pos[g.t[r]];
                 uint64_t pc = 0;

@@ -268,17 +268,11 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
 // Long runs: every term adds its angle (a fixed-point fraction of a turn,
 // so sums wrap exactly modulo a full turn) to the elements it matches; each
 // element then takes one factor exp(2 pi i acc / 2^bits), or, when every
-// term is a factor of -1, one sign flip.  complex64 keeps 32-bit turns
-// (angle error below 2^-32 turns per term), complex128 64-bit turns.
+// term is a factor of -1, one sign flip.  complex64 keeps 32-bit turns (each
+// term's angle rounded to 2^-32 turns by the planner), complex128 64-bit.
 template <typename R> struct Turn;
-template <> struct Turn<float> {
-    using T = uint32_t;
-    static __device__ __forceinline__ T from(uint64_t t) { return (uint32_t)((t + (1ull << 31)) >> 32); }
-};
-template <> struct Turn<double> {
-    using T = uint64_t;
-    static __device__ __forceinline__ T from(uint64_t t) { return t; }
-};
+template <> struct Turn<float> { using T = uint32_t; };
+template <> struct Turn<double> { using T = uint64_t; };
 
 // (cos, sin) of 2 pi t / 2^32: the quadrant from the top two bits, the angle
 // inside it folded to [0, pi/4] (sin and cos exchanged past pi/4), then the
@@ -320,38 +314,39 @@ __device__ __forceinline__ void cis_turns(uint64_t t, double& c, double& s) {
 }
 
 template <typename R, int L>
-__device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DSub* __restrict__ subs,
-                                                   int nsub, uint64_t base, bool signs) {
+__device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DTerm* __restrict__ terms,
+                                                   const uint32_t* __restrict__ grp, uint64_t base,
+                                                   bool signs) {
     using TU = typename Turn<R>::T;
     constexpr uint32_t nE = 1u << L;
-    constexpr int NROW = nE >= NT ? (int)(nE / NT) : 1;   // elements per thread
-    constexpr int NPT = NROW < 8 ? NROW : 8;               // elements per sweep
-    constexpr uint32_t LOWM = NT - 1;
+    constexpr int NHB = L > kLogTileThreads ? L - kLogTileThreads : 0;   // element bits
+    constexpr int NE = 1 << NHB;                                          // elements per thread
     const uint32_t t = threadIdx.x;
-#pragma unroll 1
-    for (int i0 = 0; i0 < NROW; i0 += NPT) {
-    TU acc[NPT];
+    // one sum per group of terms (per set of element bits they require)
+    TU acc[NE];
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) acc[i] = 0;
+    for (int g = 0; g < NE; ++g) {
+        TU a = 0;
+        const uint32_t q1 = grp[g + 1];
 #pragma unroll 1
-    for (int q = 0; q < nsub; ++q) {
-        const DSub& d = subs[q];
-        if ((base & d.omask) != d.oval) continue;
-        const TU tv = Turn<R>::from(d.turns);
-        const TU a = (t & d.lmask & LOWM) == (d.lval & LOWM) ? tv : (TU)0;
-        const uint32_t rows = d.rows >> i0;
-        // all-ones or zero per element (one scalar bit extract), so the add
-        // needs no per-element branch or compare
-#pragma unroll
-        for (int i = 0; i < NPT; ++i) {
-            const TU m = (TU)(-(typename std::make_signed<TU>::type)((rows >> i) & 1));
-            acc[i] += a & m;
+        for (uint32_t q = grp[g]; q < q1; ++q) {
+            const DTerm& d = terms[q];
+            if ((base & d.omask) != d.oval) continue;
+            a += (t & d.lmask) == d.lval ? (TU)d.turns : (TU)0;
         }
+        acc[g] = a;
     }
+    // subset sums over the element bits: element i collects every group S
+    // with S contained in i
+#pragma unroll
+    for (int b = 0; b < NHB; ++b)
+#pragma unroll
+        for (int i = 0; i < NE; ++i)
+            if ((i >> b) & 1) acc[i] += acc[i ^ (1 << b)];
     if (t >= nE) return;
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-        const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+    for (int i = 0; i < NE; ++i) {
+        const uint32_t s = 2 * sw(t + NT * (uint32_t)i);
         const R xr = lds[s], xi = lds[s + 1];
         if (signs) {
             // the accumulated angle is 0 or a half turn
@@ -364,7 +359,6 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DS
             lds[s] = fr * xr - fi * xi;
             lds[s + 1] = fr * xi + fi * xr;
         }
-    }
     }
 }
 
@@ -464,7 +458,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
             }
         } else {
             if (op.flags & DRUN_TURNS)
-                tile_diagrun_turns<R, L>(lds, (const DSub*)(blob + op.data), op.k, base,
+                tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data),
+                                         (const uint32_t*)(blob + op.tab), base,
                                          (op.flags & DRUN_SIGNS) != 0);
             else
                 tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);

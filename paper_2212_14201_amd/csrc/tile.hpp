@@ -26,7 +26,8 @@ struct TOp {
     uint64_t data;          // byte offset into the plan blob: fragments or DSub[k]
     int32_t next_block;     // index of the pass's next TOP_BLOCK op, -1 if none
     int32_t flags;          // diagonal run: DRUN_* bits
-    uint64_t tab;           // block: byte offset of its address table (BlockTab layout)
+    uint64_t tab;           // block: byte offset of its address table (BlockTab layout);
+                            // angle-path diagonal run: byte offset of its group offsets
 };
 
 // LDS slot of tile element e: bits 1..3 are XOR-ed with bits 4..6 and 8..10
@@ -61,6 +62,8 @@ struct BlockTabLayout {
 };
 
 constexpr int kTileThreads = 512;    // threads per tile workgroup (8 waves)
+constexpr int kLogTileThreads = 9;
+static_assert(1 << kLogTileThreads == kTileThreads, "kLogTileThreads");
 
 // One phase term of a diagonal run: amplitudes whose local tile bits match
 // (lmask, lval) and whose tile's outer bits match (omask, oval) are
@@ -79,6 +82,24 @@ struct DSub {
     uint64_t pad2_;         // 64 bytes: read as four 16-byte words
 };
 static_assert(sizeof(DSub) == 64, "DSub is read as four 16-byte words");
+
+// One term of a diagonal run on the angle path (DRUN_TURNS).  Thread t holds
+// elements t + kTileThreads i, i < 2^h (h = L - kLogTileThreads element
+// bits).  A term adds `turns` (the kernel's fixed-point width: the low 32
+// bits for complex64, all 64 for complex128) to element (t, i) when the
+// tile's outer bits match (omask, oval), t matches (lmask, lval) on the
+// thread bits, and i has every element bit of the term's group set.  The
+// run's terms are stored grouped by that element-bit set S, with group
+// offsets (2^h + 1 words, TOp::tab); each thread sums its groups and a
+// subset-sum over the element bits gives element i the total of every group
+// S contained in i.  A condition h_j = 0 on an element bit is rewritten as
+// 1 - h_j on the host, so every term's element condition is a set of ones.
+struct DTerm {
+    uint64_t omask, oval;
+    uint64_t turns;
+    uint32_t lmask, lval;   // thread bits only
+};
+static_assert(sizeof(DTerm) == 32, "DTerm layout");
 
 struct PassDesc {
     int32_t L;              // tile qubits

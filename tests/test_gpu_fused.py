@@ -179,8 +179,9 @@ def diagonal_heavy_circuit(n, seed):
     return gates
 
 
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,tile", [(14, 10), (16, 12), (12, 12)])
+@pytest.mark.parametrize("dtype,n,tile", [(d, n, t) for d in ("c128", "c64")
+                                          for n, t in ((14, 10), (16, 12), (12, 12))]
+                         + [("c64", 13, 13), ("c64", 18, 13), ("c64", 8, 8)])
 def test_fused_long_diagonal_runs(n, tile, dtype):
     gates = diagonal_heavy_circuit(n, 900 + n + tile)
     sv, plan = run_fused(n, gates, dtype, 3, tile, init=0)

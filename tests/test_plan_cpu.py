@@ -189,3 +189,104 @@ def test_plan_flags_rejected():
     h = qvm.ctypes.c_void_p()
     st = L.qvm_plan_greedy_ex(ga.ptr(), ga.n, 3, 3, 0, qvm.QVM_C64, 2, qvm.ctypes.byref(h))
     assert qvm.STATUS[st] == "QVM_EARG" and not h.value
+
+
+# Device-image records of the tile kernel (layouts in csrc/tile.hpp).
+_PD = np.dtype([("L", "<i4"), ("c", "<i4"), ("nops", "<i4"), ("remap", "<i4"), ("kmax", "<i4"),
+                ("first_block", "<i4"), ("qmask", "<u8"), ("ops", "<u8"), ("ldoff", "<u8"),
+                ("rmhi", "<u8"), ("rmlo", "<u8")])
+_TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"),
+                 ("next_block", "<i4"), ("flags", "<i4"), ("tab", "<u8")])
+_DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
+                  ("oval", "<u8"), ("pr", "<f8"), ("pi", "<f8"), ("turns", "<u8"), ("pad", "<u8")])
+_DTERM = np.dtype([("omask", "<u8"), ("oval", "<u8"), ("turns", "<u8"), ("lmask", "<u4"), ("lval", "<u4")])
+
+
+def plan_image(plan):
+    import ctypes
+    L = qvm.lib()
+    L.qvm_plan_image.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_int32)]
+    nb, pt, npass = ctypes.c_size_t(), ctypes.c_uint64(), ctypes.c_int32()
+    qvm.check(L.qvm_plan_image(plan._h, None, 0, ctypes.byref(nb), ctypes.byref(pt), ctypes.byref(npass)))
+    buf = np.zeros(nb.value, np.uint8)
+    qvm.check(L.qvm_plan_image(plan._h, buf.ctypes.data, nb.value, None, None, None))
+    rec = lambda off, dt, cnt: np.frombuffer(buf[off: off + cnt * dt.itemsize].tobytes(), dt)
+    return rec, rec(pt.value, _PD, npass.value)
+
+
+def emulate_diagonal_pass(plan, n, width):
+    """Phase of every basis index after the single pass of a plan over a
+    diagonal-only circuit, from the image's diagonal runs: term-by-term
+    factors for short runs; grouped angle sums and the subset-sum over the
+    element bits for angle-path runs."""
+    rec, passes = plan_image(plan)
+    assert len(passes) == 1 and passes[0]["L"] == n
+    pd = passes[0]
+    L, c = n, int(pd["c"])
+    ldoff = rec(int(pd["ldoff"]), np.dtype("<u8"), 1 << (L - c))
+    e = np.arange(1 << L, dtype=np.uint64)
+    phys = (e & np.uint64((1 << c) - 1)) | ldoff[(e >> np.uint64(c)).astype(np.int64)]
+    nt = 512
+    nhb = max(L - 9, 0)
+    t = np.arange(min(nt, 1 << L), dtype=np.uint64)
+    wmask = np.uint64((1 << width) - 1) if width < 64 else np.uint64(~np.uint64(0))
+    phase = np.ones(1 << L, np.complex128)
+    n_turns = 0
+    for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
+        assert op["type"] == 2
+        if op["flags"] & 1:
+            n_turns += 1
+            terms = rec(int(op["data"]), _DTERM, int(op["k"]))
+            off = rec(int(op["tab"]), np.dtype("<u4"), (1 << nhb) + 1)
+            assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) >= 0)
+            acc = np.zeros((1 << nhb, len(t)), np.uint64)
+            for g in range(1 << nhb):
+                for d in terms[off[g]: off[g + 1]]:
+                    assert d["oval"] == 0 and d["lmask"] < nt and d["lval"] & ~d["lmask"] == 0
+                    hit = (t & np.uint64(d["lmask"])) == np.uint64(d["lval"])
+                    acc[g] = (acc[g] + np.where(hit, d["turns"], np.uint64(0))) & wmask
+            for b in range(nhb):
+                for i in range(1 << nhb):
+                    if (i >> b) & 1:
+                        acc[i] = (acc[i] + acc[i ^ (1 << b)]) & wmask
+            ang = acc.reshape(-1)              # element t + 512 i at i * len(t) + t
+            if op["flags"] & 2:
+                phase *= np.where(ang >> np.uint64(width - 1), -1.0, 1.0)
+            else:
+                phase *= np.exp(2j * np.pi * (ang.astype(np.float64) / 2.0 ** width))
+        else:
+            for d in rec(int(op["data"]), _DSUB, int(op["k"])):
+                hit = (e & np.uint64(d["lmask"])) == np.uint64(d["lval"])
+                f = -1.0 if d["neg"] else d["pr"] + 1j * d["pi"]
+                phase = np.where(hit, phase * f, phase)
+    out = np.zeros(1 << n, np.complex128)
+    out[phys.astype(np.int64)] = phase
+    return out, n_turns
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 13), ("c64", 11), ("c128", 12), ("c64", 8)])
+def test_angle_path_encoding_reproduces_diagonal(dtype, n):
+    """Pins the planner's encoding of long diagonal runs (element-bit zeros
+    rewritten as 1 - h, merged terms, grouped sums, subset sums) against
+    the oracle: on a diagonal-only circuit the state from the uniform
+    superposition carries exactly the circuit's diagonal."""
+    rng = np.random.Generator(np.random.PCG64(77 + n))
+    gates = []
+    for _ in range(60):
+        kind = int(rng.integers(0, 7))
+        a, b, cq = (int(v) for v in rng.choice(n, 3, replace=False))
+        th = float(rng.uniform(0, 2 * np.pi))
+        gates.append([Gate("rz", (a,), (), (th,)), Gate("rzz", (a, b), (), (th,)),
+                      Gate("p", (a,), (b,), (th,)), Gate("t", (a,)), Gate("sdg", (a,)),
+                      Gate("p", (a,), (b, cq), (th,)), Gate("rz", (a,), (b,), (th,))][kind])
+    signs = [Gate("z", (int(q),), (int(r),)) for q, r in rng.integers(0, n, (12, 2)) if q != r]
+    for gl, only_signs in ((gates, False), (signs, True)):
+        plan = qvm.Plan(gl, n, dtype, k_max=3, tile_qubits=n)
+        got, n_turns = emulate_diagonal_pass(plan, n, 32 if dtype == "c64" else 64)
+        assert n_turns >= 1
+        psi = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+        want = oracle.apply_gates(psi, n, gl) * 2.0 ** (n / 2)
+        tol = 1e-7 if dtype == "c64" else 1e-12
+        assert np.max(np.abs(got - want)) < tol, (only_signs, np.max(np.abs(got - want)))
