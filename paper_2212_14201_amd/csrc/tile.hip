@@ -346,18 +346,18 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     if (t >= nE) return;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        const uint32_t s = 2 * sw(t + NT * (uint32_t)i);
-        const R xr = lds[s], xi = lds[s + 1];
+        const uint32_t e = 2 * sw(t + NT * (uint32_t)i);
+        const R xr = lds[e], xi = lds[e + 1];
         if (signs) {
             // the accumulated angle is 0 or a half turn
             const R sg = (acc[i] >> (8 * sizeof(TU) - 1)) ? (R)-1 : (R)1;
-            lds[s] = sg * xr;
-            lds[s + 1] = sg * xi;
+            lds[e] = sg * xr;
+            lds[e + 1] = sg * xi;
         } else {
             R fr, fi;
             cis_turns(acc[i], fr, fi);
-            lds[s] = fr * xr - fi * xi;
-            lds[s + 1] = fr * xi + fi * xr;
+            lds[e] = fr * xr - fi * xi;
+            lds[e + 1] = fr * xi + fi * xr;
         }
     }
 }
@@ -468,7 +468,11 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     }
 
     // store: per batch, LDS reads first (optionally through the tile-bit
-    // remap), then the global stores
+    // remap), then the global stores.  The slots and chunk offsets are
+    // computed again rather than kept in registers from the load phase
+    // through every op (the opaque copy of the thread index stops the reuse).
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (live) {
         const uint32_t* __restrict__ rmhi = (const uint32_t*)(blob + pd.rmhi);
         const uint32_t* __restrict__ rmlo = (const uint32_t*)(blob + pd.rmlo);
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
             if (!remap) {
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t d = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                    const uint32_t d = (tid + NT * (uint32_t)(b0 + it)) * EP;
                     v[it] = *(const V16*)(lds + 2 * sw(d));
                 }
             } else {
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 uint32_t hi[BATCH], lo0[BATCH], lo1[BATCH];
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t d = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                    const uint32_t d = (tid + NT * (uint32_t)(b0 + it)) * EP;
                     hi[it] = rmhi[d >> C];
                     lo0[it] = rmlo[d & CM];
                     lo1[it] = EP == 2 ? rmlo[(d + 1) & CM] : 0u;
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
             }
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
-                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                const uint32_t e = (tid + NT * (uint32_t)(b0 + it)) * EP;
                 __builtin_nontemporal_store(v[it], (V16*)(psi + 2 * (base + ldoff[e >> C] + (e & CM))));
             }
         }
