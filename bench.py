@@ -159,6 +159,43 @@ def adjoint_measure(torch, reps=2):
             "effective_GBs": per * B / dt / 1e9, "frac_of_hbm_peak": per * B / dt / 1e9 / HBM_PEAK_GBS}
 
 
+def noise_measure(torch, reps=3):
+    """Kraus trajectories: 26 qubits, complex64, 4 layers of RY + RZ on every
+    qubit, a CNOT / CZ brick and an H (262 gates), with depolarizing noise
+    after every RY, amplitude damping on both qubits of every CNOT, phase
+    damping after every RZ and bit flips after every H.  Each branching is
+    one FP64 pass for the qubit's reduced density matrix plus the chosen
+    operator's plain-kernel pass."""
+    import numpy as np
+    from paper_2212_14201_amd import noise, profiling, qvm
+    from workloads import noisy_layers, uniform_stream
+    n, layers = 26, 4
+    gates = noisy_layers(n, layers, 2600)
+    model = noise.NoiseModel([("ry", "depolarizing", {"p": 0.01}), ("cnot", "damping", {"p": 0.02}),
+                              ("rz", "phase_damping", {"p": 0.02}), ("h", "bit_flip", {"p": 0.01})])
+    nb = model.branchings(gates)
+    sv = qvm.StateVector(n, "c64")
+    u = uniform_stream(2601, nb * (reps + 1))
+    noise.run_trajectory(sv, gates, model, u[:nb])
+    torch.cuda.synchronize()
+    profiling.begin(sv)
+    t0 = time.perf_counter()
+    for r in range(reps):
+        noise.run_trajectory(sv, gates, model, u[nb * (r + 1): nb * (r + 2)])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    st = profiling.end(sv).get("rdm1", {})
+    ms = st.get("total_ms", 0.0)
+    gbs = st["bytes"] / (ms / 1e3) / 1e9 if ms else None
+    return {"workload": f"{n} qubits, complex64, {len(gates)} gates, {nb} Kraus branchings "
+                        "(depolarizing, damping, phase damping, bit flip)",
+            "ms_per_trajectory": dt * 1e3, "trajectories_per_s": 1.0 / dt,
+            "branchings_per_s": nb / dt,
+            "rdm1_kernel": {"launches": st.get("launches"), "avg_launch_ms":
+                            ms / st["launches"] if ms else None, "GBs": gbs,
+                            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS if gbs else None}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +207,7 @@ def main():
     ap.add_argument("--k-max", type=int, default=4)
     ap.add_argument("--tile", type=int, default=13, help="tile qubits per pass (0: one block per pass)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
+    ap.add_argument("--no-noise", action="store_true", help="skip the Kraus-trajectory workload")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 comparison path")
@@ -344,6 +382,8 @@ def main():
         out["plain_c128"]["frac_of_copy"] = out["plain_c128"]["effective_GBs"] / out["hbm_copy_GBs"]
     if not args.no_adjoint:
         out["adjoint_c64"] = adjoint_measure(torch)
+    if not args.no_noise:
+        out["noise_c64"] = noise_measure(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, x, gates, args.cpu_seconds, plain_bytes)
     print(json.dumps(out), flush=True)

@@ -126,6 +126,24 @@ qvm_status qvm_init_basis(qvm_sv* sv, uint64_t index);
  * dense matrices; any number of controls.  Asynchronous. */
 qvm_status qvm_apply(qvm_sv* sv, const qvm_gate* g);
 
+/* One single-qubit Kraus channel by the trajectory method (paper, "Noise
+ * simulation method": noise models given as Kraus operators K_1..K_m; a noisy
+ * run unravels each channel into one randomly drawn branch).  ops holds
+ * n_ops (1..16) 2x2 complex matrices as (re, im) doubles, row-major, 8 per
+ * operator (host memory, read during the call).  The branch weights
+ * p_i = ||K_i psi||^2 = Tr(K_i^dag K_i rho_q) come from the qubit's reduced
+ * density matrix rho_q, accumulated in FP64 in one pass over the state; the
+ * branch j is the smallest with p_1 + ... + p_j > u (p_1 + ... + p_m), and
+ * psi <- K_j psi sqrt((p_1 + ... + p_m) / p_j), which keeps the state's norm.
+ * u is the caller's uniform in [0, 1).  chosen (nullable) receives j
+ * (0-based); probs (nullable, n_ops doubles) receives p_i / sum.  Operators
+ * need not be unitary or complete (the weights are normalised by their sum).
+ * Synchronizes the stream.  QVM_ERANGE: qubit >= n; QVM_EARG: n_ops outside
+ * 1..16, NULL ops, u outside [0, 1), or every weight zero. */
+#define QVM_MAX_KRAUS 16
+qvm_status qvm_apply_kraus(qvm_sv* sv, int32_t qubit, int32_t n_ops, const double* ops, double u,
+                           int32_t* chosen, double* probs);
+
 /* Apply a gate list in order with the plain per-gate path, in one call (the
  * per-gate call overhead the paper measures at small n is paid once).
  * The list is validated in full before anything is enqueued. */
@@ -381,7 +399,7 @@ qvm_status qvm_stream_copy(void* dst, const void* src, size_t bytes, void* strea
  * flops (complex multiply-adds of dense and fused matrices, 8 flops each).
  * Used to report achieved bandwidth and throughput against the roofline. */
 typedef struct qvm_kernel_stat {
-    char name[24];           /* dense1..dense3, diag, phase, swappair, tile, basis */
+    char name[24];           /* dense1..dense3, diag, phase, swappair, tile, basis, rdm1 */
     int64_t launches;
     double total_ms;
     double bytes;
@@ -397,7 +415,7 @@ qvm_status qvm_profile_begin(qvm_sv* sv);
 qvm_status qvm_profile_end(qvm_sv* sv, qvm_kernel_stat* out, int32_t max, int32_t* count);
 
 /* Per-launch durations (ms) and kernel classes (index into the class list
- * above: 0 dense1 .. 7 basis) of the last profiled interval, in launch
+ * above: 0 dense1 .. 7 basis, 8 rdm1) of the last profiled interval, in launch
  * order; up to max entries, *count = the number recorded. */
 qvm_status qvm_profile_launches(const qvm_sv* sv, double* ms, int32_t* kind, int32_t max,
                                 int32_t* count);

@@ -344,6 +344,48 @@ qvm_status qvm_apply(qvm_sv* sv, const qvm_gate* g) {
     return launch_op(sv, lower(sv, *g, u));
 }
 
+qvm_status qvm_apply_kraus(qvm_sv* sv, int32_t qubit, int32_t n_ops, const double* ops, double u,
+                           int32_t* chosen, double* probs) {
+    QVM_CHECK_SV(sv);
+    if (qubit < 0 || qubit >= sv->n) return fail(QVM_ERANGE, "qubit >= n");
+    if (n_ops < 1 || n_ops > QVM_MAX_KRAUS) return fail(QVM_EARG, "n_ops outside 1..16");
+    if (!ops) return fail(QVM_EARG, "NULL Kraus operators");
+    if (!(u >= 0.0 && u < 1.0)) return fail(QVM_EARG, "u outside [0, 1)");
+    // reduced density matrix of the qubit: rho = [[r00, r01], [conj(r01), r11]]
+    double r[4];
+    qvm_status st = rd_rdm1(sv, sv->perm[qubit], r);
+    if (st) return st;
+    const cd r01(r[2], r[3]);
+    // p_i = ||K_i psi||^2 = Tr(K_i^dag K_i rho)
+    double w[QVM_MAX_KRAUS], total = 0;
+    for (int i = 0; i < n_ops; ++i) {
+        const double* k = ops + 8 * i;
+        const cd a(k[0], k[1]), b(k[2], k[3]), c(k[4], k[5]), d(k[6], k[7]);
+        const double m00 = std::norm(a) + std::norm(c), m11 = std::norm(b) + std::norm(d);
+        const cd m01 = std::conj(a) * b + std::conj(c) * d;          // (K^dag K)_{01}
+        // Tr(M rho) = m00 r00 + m11 r11 + 2 Re(m01 conj(r01))
+        w[i] = std::max(0.0, m00 * r[0] + m11 * r[1] + 2.0 * (m01 * std::conj(r01)).real());
+        total += w[i];
+    }
+    if (!(total > 0.0)) return fail(QVM_EARG, "every Kraus branch has zero weight");
+    int j = 0;
+    for (double acc = w[0]; j < n_ops - 1 && !(acc > u * total); acc += w[++j]) {}
+    while (w[j] == 0.0 && j > 0) --j;                 // rounding at the top end
+    const double f = std::sqrt(total / w[j]);        // keeps the state's norm
+    std::vector<cd> m(4);
+    for (int e = 0; e < 4; ++e) m[e] = f * cd(ops[8 * j + 2 * e], ops[8 * j + 2 * e + 1]);
+    qvm_gate g{};
+    g.kind = QVM_G_MATRIX;
+    g.k = 1;
+    g.targets[0] = qubit;
+    st = launch_op(sv, lower(sv, g, m));
+    if (st) return st;
+    if (chosen) *chosen = j;
+    if (probs)
+        for (int i = 0; i < n_ops; ++i) probs[i] = w[i] / total;
+    return QVM_OK;
+}
+
 qvm_status qvm_run(qvm_sv* sv, const qvm_gate* gates, size_t n_gates) {
     QVM_CHECK_SV(sv);
     if (n_gates && !gates) return fail(QVM_EARG, "NULL gate list");

@@ -35,7 +35,7 @@ constexpr int kRedSlots = 64;         // doubles per block in the partials table
 
 // Per-launch timing with HIP events (enabled by qvm_profile_begin).
 enum ProfKind { PK_DENSE1 = 0, PK_DENSE2, PK_DENSE3, PK_DIAG, PK_PHASE, PK_SWAP, PK_TILE,
-                PK_BASIS, PK_COUNT };
+                PK_BASIS, PK_RDM1, PK_COUNT };
 struct ProfRec {
     int kind;
     int ev;                           // index of the start event; end = ev + 1
@@ -118,6 +118,9 @@ qvm_status launch_swap_bits(qvm_sv* sv, int a, int b);   // physical bit swap
 qvm_status rd_norm(qvm_sv* sv, double* out);
 qvm_status rd_scale(qvm_sv* sv, double factor);
 qvm_status rd_z_all(qvm_sv* sv, double* out_phys_total, double* out_phys_bit);
+// out = {sum |psi_i|^2 over physical bit pbit = 0, the same over bit = 1,
+//        Re and Im of sum psi_i conj(psi_{i | 2^pbit})}, FP64; synchronizes
+qvm_status rd_rdm1(qvm_sv* sv, int pbit, double* out);
 qvm_status rd_pauli_group(qvm_sv* sv, uint64_t x_phys, int nt, const uint64_t* z_phys,
                           double* out);
 qvm_status rd_probs_full(qvm_sv* sv, double* out_host);

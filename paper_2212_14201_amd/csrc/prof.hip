@@ -11,7 +11,7 @@
 namespace qvm {
 
 static const char* kProfNames[PK_COUNT] = {"dense1", "dense2", "dense3", "diag", "phase",
-                                           "swappair", "tile", "basis"};
+                                           "swappair", "tile", "basis", "rdm1"};
 
 int prof_begin(qvm_sv* sv) {
     if (!sv->prof.on) return -1;

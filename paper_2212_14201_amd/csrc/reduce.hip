@@ -360,6 +360,33 @@ __global__ __launch_bounds__(256) void k_gather(const typename C2r<R>::T* __rest
     out[j] = make_double2((double)v.x, (double)v.y);
 }
 
+// ------------------------------------------ one qubit's reduced density matrix
+// Over the pairs (i, j = i | 2^b) with physical bit b of i clear:
+// part row [0] = sum |psi_i|^2, [1] = sum |psi_j|^2, [2] + i [3] = sum psi_i conj(psi_j).
+template <typename R>
+__global__ __launch_bounds__(256) void k_rdm1_partial(const typename C2r<R>::T* __restrict__ psi,
+                                                      uint64_t half, int b, double* __restrict__ part) {
+    __shared__ double sh[4];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t low = (1ull << b) - 1;
+    double r00 = 0, r11 = 0, re = 0, im = 0;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < half; w += stride) {
+        const uint64_t i = ((w & ~low) << 1) | (w & low);
+        const auto x = psi[i], y = psi[i | (low + 1)];
+        const double xr = x.x, xi = x.y, yr = y.x, yi = y.y;
+        r00 += xr * xr + xi * xi;
+        r11 += yr * yr + yi * yi;
+        re += xr * yr + xi * yi;
+        im += xi * yr - xr * yi;
+    }
+    const double v[4] = {r00, r11, re, im};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double t = block_sum256(v[s], sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kRedSlots + s] = t;
+    }
+}
+
 // ============================================================ host side
 static unsigned grid_of(uint64_t items) {
     uint64_t g = (items + 255) / 256;
@@ -419,6 +446,23 @@ static qvm_status zall_t(qvm_sv* sv, double* total, double* bit) {
     *total = res[0];
     for (int q = 0; q < sv->n; ++q) bit[q] = res[1 + q];
     return QVM_OK;
+}
+
+template <typename R>
+static qvm_status rdm1_t(qvm_sv* sv, int pbit, double* out) {
+    using T = typename C2r<R>::T;
+    const int tok = prof_begin(sv);
+    hipLaunchKernelGGL((k_rdm1_partial<R>), dim3(kRedBlocks), dim3(256), 0, sv->stream,
+                       (const T*)sv->amps, 1ull << (sv->n - 1), pbit, red_part(sv));
+    prof_end(sv, tok, PK_RDM1, (double)(1ull << sv->n) * sizeof(T), 8.0 * (double)(1ull << sv->n));
+    QVM_LAUNCH_CHECK(sv);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, sv->stream, red_part(sv), 4, red_res(sv));
+    QVM_LAUNCH_CHECK(sv);
+    return fetch(sv, out, red_res(sv), 4 * sizeof(double));
+}
+
+qvm_status rd_rdm1(qvm_sv* sv, int pbit, double* out) {
+    return sv->dt == QVM_C64 ? rdm1_t<float>(sv, pbit, out) : rdm1_t<double>(sv, pbit, out);
 }
 
 qvm_status rd_z_all(qvm_sv* sv, double* total, double* bit) {

@@ -62,6 +62,8 @@ def _declare(L):
         "qvm_init_basis": (st, [_vp, ctypes.c_uint64]),
         "qvm_apply": (st, [_vp, _gp]),
         "qvm_run": (st, [_vp, _gp, ctypes.c_size_t]),
+        "qvm_apply_kraus": (st, [_vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_double,
+                                 _i32p, _dp]),
         "qvm_get_layout": (st, [_vp, _i32p]),
         "qvm_reset_layout": (st, [_vp]),
         "qvm_probabilities": (st, [_vp, ctypes.c_int, _i32p, _dp]),
@@ -257,6 +259,17 @@ class StateVector:
     def run(self, gates, params=None):
         ga = gates if isinstance(gates, GateArray) else GateArray(gates, params)
         check(lib().qvm_run(self._h, ga.ptr(), ga.n))
+
+    def apply_kraus(self, qubit: int, ops, u: float):
+        """One Kraus channel on one qubit by a trajectory branching; ops is a
+        sequence of 2x2 complex matrices.  Returns (branch, probabilities)."""
+        k = np.ascontiguousarray(np.asarray(ops, dtype=np.complex128).reshape(-1, 2, 2))
+        buf = np.ascontiguousarray(k.view(np.float64).reshape(-1))
+        j = ctypes.c_int32(-1)
+        probs = np.zeros(k.shape[0], dtype=np.float64)
+        check(lib().qvm_apply_kraus(self._h, int(qubit), k.shape[0], buf.ctypes.data_as(_dp),
+                                    float(u), ctypes.byref(j), probs.ctypes.data_as(_dp)))
+        return int(j.value), probs
 
     def layout(self):
         out = np.zeros(self.n, dtype=np.int32)

@@ -11,11 +11,11 @@ from .circuits import (Gate, layered_u3_cz, qft_circuit, qft_then_brick,
                        random_planner_circuit, random_mixed_circuit,
                        ghz_circuit, w_circuit, uniform_stream, qubits_of,
                        config_circuit, rotation_cnot_circuit, mlp_init, SEEDS,
-                       planner_mix_circuit, PLANNER_FAMILIES)
+                       planner_mix_circuit, PLANNER_FAMILIES, noisy_layers)
 
 __all__ = ["Gate", "layered_u3_cz", "qft_circuit", "qft_then_brick",
            "hardware_efficient_ansatz", "random_pauli_sum",
            "random_planner_circuit", "random_mixed_circuit", "ghz_circuit",
            "w_circuit", "uniform_stream", "qubits_of", "config_circuit",
            "rotation_cnot_circuit", "mlp_init", "SEEDS",
-           "planner_mix_circuit", "PLANNER_FAMILIES"]
+           "planner_mix_circuit", "PLANNER_FAMILIES", "noisy_layers"]

@@ -54,6 +54,22 @@ def uniform_stream(seed: int, count: int) -> np.ndarray:
     return _rng(seed).random(count)
 
 
+def noisy_layers(n: int, layers: int, seed: int):
+    """Layers of RY and RZ on every qubit (seeded angles), then a brick of
+    CNOTs and CZs, then one H on a random qubit: every gate type a noise
+    model usually names occurs many times."""
+    rng = _rng(seed)
+    g = []
+    for l in range(layers):
+        for q in range(n):
+            g.append(Gate("ry", (q,), (), (float(rng.uniform(0, TWO_PI)),)))
+            g.append(Gate("rz", (q,), (), (float(rng.uniform(0, TWO_PI)),)))
+        for q in range(l % 2, n - 1, 2):
+            g.append(Gate("x", (q + 1,), (q,)) if (q // 2 + l) % 2 == 0 else Gate("z", (q + 1,), (q,)))
+        g.append(Gate("h", (int(rng.integers(0, n)),)))
+    return g
+
+
 def _cz_brick(n: int, layer: int):
     start = 0 if layer % 2 == 0 else 1
     return [Gate("z", (i + 1,), (i,)) for i in range(start, n - 1, 2)]
