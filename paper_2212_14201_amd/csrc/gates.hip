@@ -34,13 +34,11 @@ template <typename R, int K> struct DenseArgs {
     R m[2 << (2 * K)];               // 2^K x 2^K complex, row-major (re, im)
 };
 
-// Items per thread (U) and access kind.  Measured on MI355X, an in-place
-// read-modify-write of a large buffer streams fastest with one 16-byte item
-// per thread and nontemporal loads and stores (6.6 TB/s, against 5.3-5.7
-// TB/s with 2-8 items per thread or with ordinary accesses); the state is
-// touched once per gate, so caching it gains nothing.  Items past the end
-// re-read the last item and store nothing.
-template <int K> struct Unroll { static constexpr int U = 1; };
+// Access kind.  Measured on MI355X, an in-place read-modify-write of a
+// large buffer streams fastest with one 16-byte item per thread and
+// nontemporal loads and stores (6.6 TB/s, against 5.3-5.7 TB/s with 2-8
+// items per thread or with ordinary accesses); the state is touched once per
+// gate, so caching it gains nothing.
 constexpr int kTPB = 256;                    // threads per block of the plain kernels
 
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
@@ -64,35 +62,26 @@ template <typename R, int K>
 __global__ __launch_bounds__(kTPB) void k_dense(typename C2<R>::T* __restrict__ psi,
                                                 DenseArgs<R, K> a) {
     using T = typename C2<R>::T;
-    constexpr int D = 1 << K, U = Unroll<K>::U;
-    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * U) + threadIdx.x;
-    uint64_t b[U];
-    T v[U][D];
+    constexpr int D = 1 << K;
+    const uint64_t stride = (uint64_t)gridDim.x * kTPB;
+    for (uint64_t w = (uint64_t)blockIdx.x * kTPB + threadIdx.x; w < a.items; w += stride) {
+        const uint64_t b = deposit(w, a.fixed) | a.cmask;
+        T v[D];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, a.items - 1);
-        b[u] = deposit(w, a.fixed) | a.cmask;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int j = 0; j < D; ++j) v[u][j] = ld_stream(psi + b[u] + a.off[j]);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        if (w0 + (uint64_t)kTPB * u >= a.items) break;
+        for (int j = 0; j < D; ++j) v[j] = ld_stream(psi + b + a.off[j]);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             R re = 0, im = 0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 R mr = a.m[2 * (i * D + j)], mi = a.m[2 * (i * D + j) + 1];
-                re += mr * v[u][j].x - mi * v[u][j].y;
-                im += mr * v[u][j].y + mi * v[u][j].x;
+                re += mr * v[j].x - mi * v[j].y;
+                im += mr * v[j].y + mi * v[j].x;
             }
             T o;
             o.x = re;
             o.y = im;
-            st_stream(psi + b[u] + a.off[i], o);
+            st_stream(psi + b + a.off[i], o);
         }
     }
 }
@@ -104,32 +93,20 @@ template <typename R> struct DiagArgs {
     R d[16];                          // up to 2^3 complex entries
 };
 
-constexpr int kU1 = 1;                       // items per thread, one amplitude per item
-constexpr int kU2 = 1;                       // items per thread, two amplitudes per item
-
 template <typename R>
 __global__ __launch_bounds__(kTPB) void k_diag(typename C2<R>::T* __restrict__ psi, DiagArgs<R> a) {
     using T = typename C2<R>::T;
-    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU1) + threadIdx.x;
-    uint64_t idx[kU1];
-    T v[kU1];
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) {
-        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, a.items - 1);
-        idx[u] = deposit(w, a.cmask) | a.cmask;
-    }
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) v[u] = ld_stream(psi + idx[u]);
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) {
-        if (w0 + (uint64_t)kTPB * u >= a.items) break;
+    const uint64_t stride = (uint64_t)gridDim.x * kTPB;
+    for (uint64_t w = (uint64_t)blockIdx.x * kTPB + threadIdx.x; w < a.items; w += stride) {
+        const uint64_t idx = deposit(w, a.cmask) | a.cmask;
+        const T v = ld_stream(psi + idx);
         int j = 0;
-        for (int r = 0; r < a.k; ++r) j |= (int)((idx[u] >> a.t[r]) & 1) << r;
+        for (int r = 0; r < a.k; ++r) j |= (int)((idx >> a.t[r]) & 1) << r;
         const R dr = a.d[2 * j], di = a.d[2 * j + 1];
         T o;
-        o.x = dr * v[u].x - di * v[u].y;
-        o.y = dr * v[u].y + di * v[u].x;
-        st_stream(psi + idx[u], o);
+        o.x = dr * v.x - di * v.y;
+        o.y = dr * v.y + di * v.x;
+        st_stream(psi + idx, o);
     }
 }
 
@@ -137,23 +114,14 @@ template <typename R>
 __global__ __launch_bounds__(kTPB) void k_phase(typename C2<R>::T* __restrict__ psi, uint64_t items,
                                                 uint64_t cmask, uint64_t cval, R pr, R pi) {
     using T = typename C2<R>::T;
-    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU1) + threadIdx.x;
-    uint64_t idx[kU1];
-    T v[kU1];
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) {
-        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, items - 1);
-        idx[u] = deposit(w, cmask) | cval;
-    }
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) v[u] = ld_stream(psi + idx[u]);
-#pragma unroll
-    for (int u = 0; u < kU1; ++u) {
-        if (w0 + (uint64_t)kTPB * u >= items) break;
+    const uint64_t stride = (uint64_t)gridDim.x * kTPB;
+    for (uint64_t w = (uint64_t)blockIdx.x * kTPB + threadIdx.x; w < items; w += stride) {
+        const uint64_t idx = deposit(w, cmask) | cval;
+        const T v = ld_stream(psi + idx);
         T o;
-        o.x = pr * v[u].x - pi * v[u].y;
-        o.y = pr * v[u].y + pi * v[u].x;
-        st_stream(psi + idx[u], o);
+        o.x = pr * v.x - pi * v.y;
+        o.y = pr * v.y + pi * v.x;
+        st_stream(psi + idx, o);
     }
 }
 
@@ -161,24 +129,12 @@ template <typename R>
 __global__ __launch_bounds__(kTPB) void k_swappair(typename C2<R>::T* __restrict__ psi, uint64_t items,
                                                    uint64_t fixed, uint64_t cval, uint64_t xmask) {
     using T = typename C2<R>::T;
-    const uint64_t w0 = (uint64_t)blockIdx.x * (kTPB * kU2) + threadIdx.x;
-    uint64_t idx[kU2];
-    T a[kU2], b[kU2];
-#pragma unroll
-    for (int u = 0; u < kU2; ++u) {
-        const uint64_t w = std::min<uint64_t>(w0 + (uint64_t)kTPB * u, items - 1);
-        idx[u] = deposit(w, fixed) | cval;
-    }
-#pragma unroll
-    for (int u = 0; u < kU2; ++u) {
-        a[u] = ld_stream(psi + idx[u]);
-        b[u] = ld_stream(psi + (idx[u] ^ xmask));
-    }
-#pragma unroll
-    for (int u = 0; u < kU2; ++u) {
-        if (w0 + (uint64_t)kTPB * u >= items) break;
-        st_stream(psi + idx[u], b[u]);
-        st_stream(psi + (idx[u] ^ xmask), a[u]);
+    const uint64_t stride = (uint64_t)gridDim.x * kTPB;
+    for (uint64_t w = (uint64_t)blockIdx.x * kTPB + threadIdx.x; w < items; w += stride) {
+        const uint64_t idx = deposit(w, fixed) | cval;
+        const T a = ld_stream(psi + idx), b = ld_stream(psi + (idx ^ xmask));
+        st_stream(psi + idx, b);
+        st_stream(psi + (idx ^ xmask), a);
     }
 }
 
@@ -195,11 +151,14 @@ __global__ __launch_bounds__(256) void k_basis(typename C2<R>::T* __restrict__ p
     }
 }
 
-// Blocks that cover `items` work items at `per` items per thread (no grid
-// stride: at most 2^34 amplitudes, so the grid stays below 2^31 blocks).
-static unsigned grid_for(uint64_t items, int per) {
-    const uint64_t g = (items + (uint64_t)kTPB * per - 1) / ((uint64_t)kTPB * per);
-    return (unsigned)std::max<uint64_t>(1, g);
+// Blocks for `items` work items, one per thread, capped at 2^23 blocks: a
+// dispatch holds its size in work items as a 32-bit value, so at most 2^31
+// threads are launched and the kernels loop over the rest (a 34-qubit state
+// has up to 2^34 items; below 32 qubits every thread takes one item).
+constexpr uint64_t kMaxBlocks = 1ull << 23;
+static unsigned grid_for(uint64_t items) {
+    const uint64_t g = (items + kTPB - 1) / kTPB;
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, kMaxBlocks));
 }
 
 static inline int popc(uint64_t v) { return __builtin_popcountll(v); }
@@ -225,7 +184,7 @@ static qvm_status launch_dense_k(qvm_sv* sv, const LOp& op) {
     }
     const double touched = (double)a.items * (1 << K);
     const int tok = prof_begin(sv);
-    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items, Unroll<K>::U)), dim3(kTPB), 0, sv->stream,
+    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(kTPB), 0, sv->stream,
                        (T*)sv->amps, a);
     QVM_LAUNCH_CHECK(sv);
     prof_end(sv, tok, PK_DENSE1 + K - 1, 2.0 * touched * sizeof(T), touched * 8.0 * (1 << K));
@@ -240,7 +199,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
             if (op.phase == cd(1.0, 0.0)) return QVM_OK;   // identity
             uint64_t items = 1ull << (sv->n - popc(op.cond_mask));
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items, kU1)), dim3(kTPB), 0, sv->stream,
+            hipLaunchKernelGGL((k_phase<R>), dim3(grid_for(items)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, items, op.cond_mask, op.cond_val,
                                (R)op.phase.real(), (R)op.phase.imag());
             QVM_LAUNCH_CHECK(sv);
@@ -259,7 +218,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
                 a.d[2 * j + 1] = (R)op.m[j].imag();
             }
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items, kU1)), dim3(kTPB), 0, sv->stream,
+            hipLaunchKernelGGL((k_diag<R>), dim3(grid_for(a.items)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, a);
             QVM_LAUNCH_CHECK(sv);
             prof_end(sv, tok, PK_DIAG, 2.0 * a.items * sizeof(T), 6.0 * a.items);
@@ -269,7 +228,7 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
             uint64_t fixed = op.cond_mask | op.hbit;
             uint64_t items = 1ull << (sv->n - popc(fixed));
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items, kU2)), dim3(kTPB), 0, sv->stream,
+            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(kTPB), 0, sv->stream,
                                (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
             QVM_LAUNCH_CHECK(sv);
             prof_end(sv, tok, PK_SWAP, 4.0 * items * sizeof(T), 0.0);
@@ -294,10 +253,10 @@ qvm_status launch_init_basis(qvm_sv* sv, uint64_t idx) {
     uint64_t N = 1ull << sv->n;
     const int tok = prof_begin(sv);
     if (sv->dt == QVM_C64)
-        hipLaunchKernelGGL((k_basis<float>), dim3(std::min<unsigned>(grid_for(N, 1), 1u << 20)), dim3(kTPB), 0, sv->stream,
+        hipLaunchKernelGGL((k_basis<float>), dim3(std::min<unsigned>(grid_for(N), 1u << 20)), dim3(kTPB), 0, sv->stream,
                            (float2*)sv->amps, N, idx);
     else
-        hipLaunchKernelGGL((k_basis<double>), dim3(std::min<unsigned>(grid_for(N, 1), 1u << 20)), dim3(kTPB), 0, sv->stream,
+        hipLaunchKernelGGL((k_basis<double>), dim3(std::min<unsigned>(grid_for(N), 1u << 20)), dim3(kTPB), 0, sv->stream,
                            (double2*)sv->amps, N, idx);
     QVM_LAUNCH_CHECK(sv);
     prof_end(sv, tok, PK_BASIS, (double)N * (sv->dt == QVM_C64 ? 8 : 16), 0.0);

@@ -5,6 +5,7 @@
 // with like.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "internal.hpp"
@@ -15,8 +16,9 @@ typedef float sc_f4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_stream_copy(const sc_f4* __restrict__ src, sc_f4* __restrict__ dst,
                                                      uint64_t pieces) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < pieces) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < pieces; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace qvm
@@ -32,8 +34,9 @@ extern "C" qvm_status qvm_stream_copy(void* dst, const void* src, size_t bytes, 
     const char* s = (const char*)src;
     const char* d = (const char*)dst;
     if (s < d + bytes && d < s + bytes) return fail(QVM_EARG, "stream copy: buffers overlap");
-    const uint64_t blocks = (pieces + 255) / 256;
-    if (blocks > 0x7fffffffull) return fail(QVM_ERANGE, "stream copy: too large for one launch");
+    // at most 2^23 blocks (a dispatch counts its threads in 32 bits); larger
+    // copies loop
+    const uint64_t blocks = std::min<uint64_t>((pieces + 255) / 256, 1ull << 23);
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        (const sc_f4*)src, (sc_f4*)dst, pieces);
     const hipError_t e = hipGetLastError();

@@ -1,6 +1,8 @@
 """Full-size parity: the 28-qubit layered workload and the 30-qubit
 QFT + brick workload (in the configuration bench.py times) against values
-the FP64 oracle stored in tests/golden/ (written by make_golden.py)."""
+the FP64 oracle stored in tests/golden/ (written by make_golden.py), and
+the largest state the library accepts (34 qubits) against the oracle's
+result on the qubits its circuit touches."""
 import json
 import math
 import os
@@ -8,8 +10,9 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 from tests.util import C128_TOL, U32, c64_bound, gate_ks
-from workloads import config_circuit
+from workloads import Gate, config_circuit, random_mixed_circuit
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -115,3 +118,51 @@ def test_qft_brick_30_qubits_bench_configuration():
     print(f"fused c64 amp err {ferr:.2e} (tol {tol:.1e}) <Z> {fz:.2e}; plain c128 amp err {perr:.2e} <Z> {pz:.2e}")
     assert perr <= C128_TOL and pz <= 1e-12
     assert ferr <= tol and fz <= 2 * tol + tol * tol
+
+
+@pytest.mark.parametrize("path", ["plain", "fused"])
+def test_maximum_size_34_qubits(path):
+    """The largest state the library accepts (34 qubits, complex64, 128 GiB):
+    a circuit on qubits 0, 11, 22 and 33 of a seeded basis state leaves the
+    state the product of the oracle's 4-qubit result and the fixed bits, so
+    every nonzero amplitude, every <Z_q> and the fixed bits of every sample
+    are known exactly."""
+    n, S = 34, (0, 11, 22, 33)
+    rng = np.random.Generator(np.random.PCG64(3434))
+    x = int(rng.integers(0, 1 << n))
+    for q in S:
+        x &= ~(1 << q)
+    small = random_mixed_circuit(4, 40, 3435, kmax=2, max_ctrl=1)
+    big = [Gate(g.name, tuple(S[t] for t in g.targets), tuple(S[c] for c in g.controls),
+                g.params, g.pidx, g.matrix) for g in small]
+    a = oracle.simulate(4, small)
+    sv = qvm.StateVector(n, "c64", init=x)
+    print(f"path={path} x={x:#x}", flush=True)
+    if path == "plain":
+        sv.run(big)
+        tol = c64_bound(gate_ks(small))
+    else:
+        plan = qvm.Plan(big, n, "c64", k_max=3, tile_qubits=13)
+        plan.run(sv)
+        sv.reset_layout()
+        tol = plan_bound(plan)
+    idx = np.array([x | sum(((j >> r) & 1) << S[r] for r in range(4)) for j in range(16)],
+                   dtype=np.uint64)
+    got = sv.gather(idx)
+    err = float(np.max(np.abs(got - a)))
+    others = np.array([(int(i) ^ (1 << 5)) for i in idx[:4]] + [int(x) ^ (1 << 30)], dtype=np.uint64)
+    zero = float(np.max(np.abs(sv.gather(others))))
+    print(f"path={path} err={err:.2e} tol={tol:.2e} off-support={zero:.1e}")
+    assert err <= tol and zero == 0.0
+    z = sv.expect_z_all()
+    pz = np.abs(a) ** 2
+    for q in range(n):
+        if q in S:
+            r = S.index(q)
+            want = sum(pz[j] * (1 - 2 * ((j >> r) & 1)) for j in range(16))
+        else:
+            want = 1.0 - 2.0 * ((x >> q) & 1)
+        assert abs(z[q] - want) <= 1e-5, q
+    smp = sv.sample(np.linspace(0.01, 0.99, 64))
+    fixed = ~sum(1 << q for q in S) & ((1 << n) - 1)
+    assert all((int(s) & fixed) == (x & fixed) for s in smp)
