@@ -233,9 +233,12 @@ typedef struct qvm_plan_stats {
 /* Greedy planner.  k_max (1..6) bounds the qubits a fused block spans.
  * tile_qubits = 0: every block gets its own pass ("one fused block per HBM
  * pass"); otherwise tile_qubits in [k_max, 13] (complex64) or [k_max, 12]
- * (complex128) and passes hold as many blocks as the tile admits.  Gate
- * validation as in qvm_run (k <= 6); a non-diagonal gate spanning more than
- * k_max qubits is QVM_EARG. */
+ * (complex128) and passes hold as many blocks as the tile admits; a tile
+ * narrower than the state must be wider than the low bits every tile holds
+ * (4 for complex64, 3 for complex128).  Gate validation as in qvm_run
+ * (k <= 6); a non-diagonal gate spanning more than k_max qubits is
+ * QVM_EARG.  n_qubits >= 3 (QVM_EUNSUPPORTED below: blocks are padded to 3
+ * qubits). */
 qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits,
                            int k_max, int tile_qubits, qvm_dtype dt,
                            qvm_plan** out);

@@ -503,6 +503,11 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
     int c = std::min(cdef, L);
     if (L < std::min(n, std::max(k_max, 3)))
         return fail(QVM_EARG, "tile too small for k_max");
+    // the lowest c physical bits are in every tile; a tile no wider than
+    // them could never take a gate on any other qubit
+    if (L < n && L <= c)
+        return fail(QVM_EARG, "tile_qubits must exceed " + std::to_string(cdef) +
+                                  " (the low bits every tile holds) when the state has more qubits");
 
     // ---- units for block / partition modes (one pass per block)
     std::vector<int> all(ngw);
@@ -538,6 +543,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
     }
     const bool tile_mode = !partition && tile_qubits != 0;
     size_t next_unit = 0;
+    int idle_passes = 0;             // consecutive tile passes that took no gate
 
     // ---- schedule, fuse and emit passes
     qvm_plan* P = new (std::nothrow) qvm_plan();
@@ -587,7 +593,13 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                     progress = true;
                 }
             }
-            if (taken.empty()) return fail_plan(QVM_EARG, "planner made no progress");
+            // Nothing fits (the next gate needs more wires outside the low
+            // bits than the tile has free slots): this pass runs no ops; it
+            // loads the wires needed soonest and its remap moves them onto
+            // the low bits (where they stay while still needed soonest), so
+            // after at most a few such passes the gate fits.
+            if (taken.empty() && ++idle_passes > n) return fail_plan(QVM_EARG, "planner made no progress");
+            if (!taken.empty()) idle_passes = 0;
             // fill the tile up to L with the wires needed soonest
             std::vector<std::pair<int, int>> nxt;
             for (int q = 0; q < n; ++q) {

@@ -179,6 +179,20 @@ def diagonal_heavy_circuit(n, seed):
     return gates
 
 
+@pytest.mark.parametrize("dtype,n,k_max,tile", [("c64", 9, 4, 5), ("c64", 10, 4, 6), ("c128", 9, 4, 4),
+                                               ("c128", 10, 4, 5), ("c128", 8, 4, 6)])
+def test_fused_narrow_tiles(dtype, n, k_max, tile):
+    """Tiles with few slots beside the always-local low bits: the plan
+    includes passes that only remap, to bring a blocked gate's wires in."""
+    gates = random_mixed_circuit(n, 60, 910 + n + tile, kmax=3, max_ctrl=1)
+    sv, plan = run_fused(n, gates, dtype, k_max, tile, init=5)
+    want = oracle.simulate(n, gates, init=5)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+    print(f"n={n} k={k_max} tile={tile} {dtype} {plan.stats()} err={err:.2e} tol={tol:.2e}")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("dtype,n,tile", [(d, n, t) for d in ("c128", "c64")
                                           for n, t in ((14, 10), (16, 12), (12, 12))]
                          + [("c64", 13, 13), ("c64", 18, 13), ("c64", 8, 8)])

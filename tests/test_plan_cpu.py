@@ -290,3 +290,22 @@ def test_angle_path_encoding_reproduces_diagonal(dtype, n):
         want = oracle.apply_gates(psi, n, gl) * 2.0 ** (n / 2)
         tol = 1e-7 if dtype == "c64" else 1e-12
         assert np.max(np.abs(got - want)) < tol, (only_signs, np.max(np.abs(got - want)))
+
+
+@pytest.mark.parametrize("dtype,c", [("c64", 4), ("c128", 3)])
+def test_narrow_tiles_plan_and_validate(dtype, c):
+    """Tiles with one to three slots beside the low bits every tile holds:
+    the scheduler inserts passes without ops whose remap brings a blocked
+    gate's wires onto the low bits; the plans are valid and their blocks
+    match the oracle.  A tile no wider than those low bits is rejected."""
+    for n in (6, 8, 9):
+        gates = random_mixed_circuit(n, 40, 900 + n, kmax=3, max_ctrl=1)
+        for free in (1, 2, 3):
+            for k in (3, 4):
+                tile = c + free
+                if tile < k or tile >= n:
+                    continue
+                plan, st = check_plan(gates, n, k, tile, dtype)
+                assert st["passes"] >= 1
+        with pytest.raises(qvm.QvmError, match="tile_qubits must exceed"):
+            qvm.Plan(gates, n, dtype, k_max=3, tile_qubits=c)
