@@ -58,7 +58,13 @@ class AdjointProblem:
         return f, g
 
 
+_FN = None
+
+
 def _function():
+    global _FN
+    if _FN is not None:
+        return _FN
     import torch
 
     class AdjointExpectation(torch.autograd.Function):
@@ -77,7 +83,8 @@ def _function():
             (g,) = ctx.saved_tensors
             return grad_f[:, None] * g, None
 
-    return AdjointExpectation
+    _FN = AdjointExpectation
+    return _FN
 
 
 def adjoint_expectation(theta, problem):

@@ -152,6 +152,67 @@ class GateArray:
         return ctypes.cast(self.arr, _gp)
 
 
+class Circuit:
+    """A circuit on n qubits under construction: a list of gate records
+    (name, targets, controls, params[, matrix]) that the library calls take
+    packed as a GateArray."""
+
+    def __init__(self, n: int, gates=()):
+        self.n = int(n)
+        self.gates = []
+        for g in gates:
+            self.add(g)
+
+    def add(self, gate):
+        qs = tuple(gate.targets) + tuple(getattr(gate, "controls", ()))
+        if any(q < 0 or q >= self.n for q in qs):
+            raise ValueError(f"gate {gate.name} acts outside qubits 0..{self.n - 1}")
+        self.gates.append(gate)
+        return self
+
+    def __len__(self):
+        return len(self.gates)
+
+    def __iter__(self):
+        return iter(self.gates)
+
+    def array(self) -> "GateArray":
+        return GateArray(self.gates)
+
+
+def plan(circuit, n: int | None = None, dtype: str = "c64", planner: str = "greedy",
+         k_max: int = 4, tile_qubits: int = 13) -> "Plan":
+    """A fused plan for a Circuit (or gate list).  planner="greedy": the
+    greedy planner at (k_max, tile_qubits); planner="learned": the shipped
+    cost model's choice among the candidate settings (needs the GPU for the
+    model and fails when no model is shipped)."""
+    if isinstance(circuit, Circuit):
+        n = circuit.n if n is None else n
+        gates = circuit.gates
+    else:
+        gates = circuit
+    if n is None:
+        raise ValueError("n is required for a plain gate list")
+    if planner == "greedy":
+        return Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile_qubits)
+    if planner == "learned":
+        from .learned_planner import load_default
+        lp = load_default()
+        if lp is None:
+            raise RuntimeError("no trained cost model is shipped with this build")
+        return lp.choose(gates if isinstance(gates, GateArray) else GateArray(gates), n, dtype)[1]
+    raise ValueError(f"unknown planner {planner!r} (greedy or learned)")
+
+
+def __getattr__(name):
+    # torch.autograd.Function over the batched adjoint gradients, built on
+    # first use (importing torch.autograd only when asked for)
+    if name == "AdjointExpectation":
+        from .adjoint import _function
+        return _function()
+    raise AttributeError(name)
+
+
 def simplify(gates, n: int) -> "GateArray":
     """The library's peephole pre-pass (qvm_simplify): identity pairs removed,
     consecutive same-axis rotations merged.  Returns a new GateArray that

@@ -82,3 +82,21 @@ def test_trained_model_gains_over_greedy():
     tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
                          + 5 * st["diag_ops"]) * U32
     assert np.max(np.abs(sv.gather(idx) - plain.gather(idx))) <= tau
+
+
+def test_plan_front_end_with_the_learned_planner():
+    """qvm.plan(circuit, planner="learned") builds the shipped model's choice
+    and the plan reproduces the oracle."""
+    from paper_2212_14201_amd import qvm
+    if lp.load_default() is None:
+        pytest.skip("no trained model shipped")
+    n, gates = random_planner_circuit(100_123, n_range=(14, 14), g_range=(120, 120))
+    c = qvm.Circuit(n, gates)
+    plan = qvm.plan(c, planner="learned")
+    sv = qvm.StateVector(n, "c64", init=3)
+    plan.run(sv)
+    want = oracle.simulate(n, gates, init=3)
+    st = plan.stats()
+    tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
+                         + 5 * st["diag_ops"]) * U32
+    assert np.max(np.abs(sv.amplitudes() - want)) <= tau

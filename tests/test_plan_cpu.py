@@ -309,3 +309,21 @@ def test_narrow_tiles_plan_and_validate(dtype, c):
                 assert st["passes"] >= 1
         with pytest.raises(qvm.QvmError, match="tile_qubits must exceed"):
             qvm.Plan(gates, n, dtype, k_max=3, tile_qubits=c)
+
+
+def test_python_layer_names():
+    """Circuit, plan(..., planner=...) and AdjointExpectation, the names the
+    Python layer offers over the C calls (host side: no GPU needed)."""
+    c = qvm.Circuit(5)
+    c.add(Gate("h", (0,))).add(Gate("x", (1,), (0,))).add(Gate("rz", (4,), (), (0.3,)))
+    assert len(c) == 3 and c.array().n == 3
+    with pytest.raises(ValueError):
+        c.add(Gate("h", (5,)))
+    p = qvm.plan(c, planner="greedy", k_max=3, tile_qubits=5)
+    assert p.stats()["passes"] >= 1
+    with pytest.raises(ValueError):
+        qvm.plan(c, planner="dynamic")
+    with pytest.raises(ValueError):
+        qvm.plan(list(c), planner="greedy")
+    adj = pytest.importorskip("paper_2212_14201_amd.adjoint")
+    assert qvm.AdjointExpectation is adj._function()
