@@ -101,6 +101,8 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
 // the lane's row bits and the k-step's row bits are disjoint, so every
 // address is a per-column constant XOR a per-lane constant XOR a
 // wave-uniform term.
+constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose fragments stay in registers
+
 template <typename R, int K>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
                                            const char* __restrict__ blob, int L) {
@@ -108,7 +110,11 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
     constexpr int k = K == 16 ? 3 : K == 32 ? 4 : K == 64 ? 5 : 6;
-    constexpr int CT = RB >= 4 ? 1 : 4 / RB;   // column tiles per wave iteration
+    // column tiles per wave iteration.  complex64: all of a wave's share of
+    // a 13-qubit tile for 3-qubit blocks (one iteration, so no column tile's
+    // loads wait behind another's stores), 4 for 4-qubit blocks; complex128
+    // (twice the accumulator registers): 4 / RB; 1 for wider blocks
+    constexpr int CT = RB >= 4 ? 1 : sizeof(R) == 8 ? 4 / RB : (K == 16 ? 8 : 4);
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int lb[6];
@@ -141,6 +147,15 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     // the lane's column inside a column tile
     const uint32_t swl = sw(dep32((uint32_t)(lane & 15), bmask));
     const R* __restrict__ Arow = ldsA + lane;
+    // small blocks keep their A fragments in registers for the whole block
+    // (the epilogue's LDS writes would otherwise force a re-read per column
+    // tile: the compiler cannot tell the tile from the fragment area)
+    constexpr int NA = K <= AREG_MAX ? RB * KS : 1;
+    R afr[NA];
+    if constexpr (K <= AREG_MAX) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) afr[i] = Arow[i * 64];
+    }
     for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
         uint32_t swe[CT];
         bool ok[CT];
@@ -156,7 +171,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) acc[ct][rb] = V4{0, 0, 0, 0};
         using V2 = typename TT<R>::V2;
-#pragma unroll 2
+#pragma unroll (K <= AREG_MAX ? KS / 2 : 2)
         for (int t = 0; t < KS / 2; ++t) {
             const uint32_t st = tab[lay.brow() + t] ^ swg;
             V2 b[CT];
@@ -166,7 +181,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
-                    const R av = Arow[(rb * KS + 2 * t + h) * 64];
+                    const R av = K <= AREG_MAX ? afr[(rb * KS + 2 * t + h) % NA]
+                                               : Arow[(rb * KS + 2 * t + h) * 64];
 #pragma unroll
                     for (int ct = 0; ct < CT; ++ct) acc[ct][rb] = mfma16(av, b[ct][h], acc[ct][rb]);
                 }
