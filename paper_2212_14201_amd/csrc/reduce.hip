@@ -250,8 +250,13 @@ __global__ __launch_bounds__(256) void k_chunk_sums(const typename C2r<R>::T* __
     __shared__ double sh[4];
     const uint64_t C = 1ull << clog;
     const uint64_t base = (uint64_t)blockIdx.x << clog;
+    // the layout map is a bit permutation, so phys(base + j + t) =
+    // phys(base) | phys(j) | phys(t) for the block's base, the uniform step j
+    // (a multiple of 256) and the thread's t < 256: one OR per element
+    const uint64_t pbt = to_phys(base, P) | to_phys(threadIdx.x, P);
     double s = 0;
-    for (uint64_t e = threadIdx.x; e < C; e += 256) s += prob(psi[to_phys(base + e, P)]);
+    for (uint64_t j = 0; j < C; j += 256)
+        if (j + threadIdx.x < C) s += prob(psi[pbt | to_phys(j, P)]);
     double r = block_sum256(s, sh);
     if (threadIdx.x == 0) csum[blockIdx.x] = r;
 }
@@ -309,8 +314,10 @@ __global__ __launch_bounds__(256) void k_find(const typename C2r<R>::T* __restri
     const uint64_t e0 = min((uint64_t)threadIdx.x * E, C);
     const uint64_t e1 = min(e0 + E, C);
     const uint64_t base = c << clog;
+    // e0 is a multiple of E, so phys(base + e0 + k) = phys(base + e0) | phys(k), k < E
+    const uint64_t pb0 = to_phys(base + e0, P);
     double loc = 0;
-    for (uint64_t e = e0; e < e1; ++e) loc += prob(psi[to_phys(base + e, P)]);
+    for (uint64_t e = e0; e < e1; ++e) loc += prob(psi[pb0 | to_phys(e - e0, P)]);
     if (threadIdx.x == 0) best = ~0ull;
     sh[threadIdx.x] = loc;
     __syncthreads();
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(256) void k_find(const typename C2r<R>::T* __restri
     double run = prefix[c] + (threadIdx.x ? sh[threadIdx.x - 1] : 0.0);
     uint64_t cand = ~0ull;
     for (uint64_t e = e0; e < e1; ++e) {
-        run += prob(psi[to_phys(base + e, P)]);
+        run += prob(psi[pb0 | to_phys(e - e0, P)]);
         if (run > target) {
             cand = base + e;
             break;
