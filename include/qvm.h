@@ -301,7 +301,8 @@ qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* plan);
  * qubits, 16 block qubits on the always-tile low bits, 17 qubits spanned by
  * the blocks' gates (before padding), 18 log2 state bytes, 19 log2 tile
  * count, 20 diagonal runs and 21 phase terms that take the angle-
- * accumulating path.  out needs cap >= n_passes * QVM_PASS_FEATURES floats
+ * accumulating path (standalone or in the epilogue of the block before
+ * them).  out needs cap >= n_passes * QVM_PASS_FEATURES floats
  * (NULL: only *n_passes is set). */
 #define QVM_PASS_FEATURES 22
 qvm_status qvm_plan_pass_features(const qvm_plan* plan, float* out, size_t cap,

@@ -337,32 +337,43 @@ uint64_t turns_of(cd v) {
     return (uint64_t)std::nearbyint(s);
 }
 
-// Angle-path terms of a long diagonal run (layout in tile.hpp): each term's
-// angle in the kernel's fixed-point width; a condition h = 0 on an element
-// bit h becomes 1 - h, so a term splits into +-angle on the supersets of its
-// required ones; terms with equal conditions in a group are merged (sums
-// modulo a full turn are exact) and zero sums dropped.  off gets 2^h + 1
-// group offsets.
-void angle_terms(const std::vector<DSub>& run, int L, qvm_dtype dt, std::vector<DTerm>& terms,
-                 std::vector<uint32_t>& off) {
-    const int nhb = L > kLogTileThreads ? L - kLogTileThreads : 0;
-    const uint32_t ne = 1u << nhb, tm = kTileThreads - 1;
+// Angle-path terms of a diagonal run (layout in tile.hpp): each term's angle
+// in the kernel's fixed-point width.  bitmap[b] says where tile bit b sits
+// in the code the kernel evaluates: a thread-code bit (0..8: the term's
+// lmask / lval) or, as 32 + j, element-code bit j (the groups).  A
+// condition h = 0 on an element bit becomes 1 - h, so a term splits into
+// +-angle on the supersets of its required ones; terms with equal
+// conditions in a group are merged (sums modulo a full turn are exact) and
+// zero sums dropped.  off gets 2^h + 1 group offsets (h element bits).
+void angle_terms(const std::vector<DSub>& run, int L, qvm_dtype dt, const int8_t* bitmap, int nhb,
+                 std::vector<DTerm>& terms, std::vector<uint32_t>& off) {
+    const uint32_t ne = 1u << nhb;
     const uint64_t wmask = dt == QVM_C64 ? 0xffffffffull : ~0ull;
     std::vector<std::vector<DTerm>> grp(ne);
     for (const DSub& d : run) {
         const uint64_t w = dt == QVM_C64 ? (d.turns + (1ull << 31)) >> 32 : d.turns;
-        const uint32_t mh = (d.lmask >> kLogTileThreads) & (ne - 1);
-        const uint32_t vh = (d.lval >> kLogTileThreads) & (ne - 1);
+        uint32_t tm = 0, tv = 0, mh = 0, vh = 0;
+        for (int b = 0; b < L; ++b) {
+            if (!((d.lmask >> b) & 1)) continue;
+            const int to = bitmap[b];
+            const uint32_t v = (d.lval >> b) & 1;
+            if (to >= 32) {
+                mh |= 1u << (to - 32);
+                vh |= v << (to - 32);
+            } else {
+                tm |= 1u << to;
+                tv |= v << to;
+            }
+        }
         const uint32_t ones = mh & vh, zeros = mh & ~vh;
         for (uint32_t T = zeros;; T = (T - 1) & zeros) {
             const uint64_t v = (__builtin_popcount(T) & 1 ? 0 - w : w) & wmask;
             std::vector<DTerm>& g = grp[ones | T];
             auto same = std::find_if(g.begin(), g.end(), [&](const DTerm& e) {
-                return e.omask == d.omask && e.oval == d.oval && e.lmask == (d.lmask & tm) &&
-                       e.lval == (d.lval & tm);
+                return e.omask == d.omask && e.oval == d.oval && e.lmask == tm && e.lval == tv;
             });
             if (same != g.end()) same->turns = (same->turns + v) & wmask;
-            else g.push_back(DTerm{d.omask, d.oval, v, d.lmask & tm, d.lval & tm});
+            else g.push_back(DTerm{d.omask, d.oval, v, tm, tv});
             if (T == 0) break;
         }
     }
@@ -373,6 +384,36 @@ void angle_terms(const std::vector<DSub>& run, int L, qvm_dtype dt, std::vector<
             if (e.turns) terms.push_back(e);
         off[g + 1] = (uint32_t)terms.size();
     }
+}
+
+// The standalone run's element layout: thread t holds elements
+// t + kTileThreads i, so tile bits below kLogTileThreads are thread bits and
+// the ones above are element bits.
+int run_bitmap(int L, int8_t* bitmap) {
+    for (int b = 0; b < L; ++b) bitmap[b] = (int8_t)(b < kLogTileThreads ? b : 32 + b - kLogTileThreads);
+    return L > kLogTileThreads ? L - kLogTileThreads : 0;
+}
+
+// The element layout of a complex64 block epilogue in a 13-qubit tile
+// (3- or 4-qubit block, one column iteration per wave; tile.hip): lane
+// l = 0..63, wave w, column tile ct < CT (8 for k = 3, 4 for k = 4) and
+// row block rb < K / 16 hold column (CT w + ct) 16 + (l & 15) of the tile
+// bits outside the block (in ascending order) and complex row
+// 8 rb + 2 (l >> 4) + hh of the block, hh = 0, 1.  Thread code:
+// (l & 15) | (l >> 4) << 4 | w << 6; element code: hh | ct << 1 | rb << (1 + log2 CT).
+bool epilogue_bitmap(const int32_t* lb, int k, int L, qvm_dtype dt, int8_t* bitmap) {
+    if (dt != QVM_C64 || L != 13 || (k != 3 && k != 4)) return false;
+    const int lct = k == 3 ? 3 : 2;
+    uint32_t bmask = 0;
+    for (int r = 0; r < k; ++r) bmask |= 1u << lb[r];
+    for (int b = 0, m = 0; b < L; ++b) {
+        if ((bmask >> b) & 1) continue;
+        bitmap[b] = (int8_t)(m < 4 ? m : m < 4 + lct ? 32 + 1 + (m - 4) : 6 + (m - 4 - lct));
+        ++m;
+    }
+    for (int r = 0; r < k; ++r)
+        bitmap[lb[r]] = (int8_t)(r == 0 ? 32 : r <= 2 ? 4 + (r - 1) : 32 + 1 + lct);
+    return true;
 }
 
 // Address table of a block op (layout in tile.hpp): the wave-uniform parts
@@ -671,16 +712,24 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             bool signs = true;
             for (const DSub& d : run) signs = signs && d.neg;
             const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
-            if ((int)run.size() >= at_least) {
+            int8_t bitmap[32];
+            const bool fuse_prev = !ops.empty() && ops.back().type == TOP_BLOCK &&
+                                   !(ops.back().flags & BLK_RUN) &&
+                                   epilogue_bitmap(ops.back().lb, ops.back().k, L, dt, bitmap);
+            if (fuse_prev || (int)run.size() >= at_least) {
+                // the angle path; right after a 3- or 4-qubit block the run
+                // is applied in that block's epilogue (no pass of its own)
+                const int nhb = fuse_prev ? 4 : run_bitmap(L, bitmap);
                 std::vector<DTerm> terms;
                 std::vector<uint32_t> off;
-                angle_terms(run, L, dt, terms, off);
+                angle_terms(run, L, dt, bitmap, nhb, terms, off);
                 run.clear();
                 if (terms.empty()) return;          // the run's phases cancel
                 op.k = (int32_t)terms.size();
-                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0);
+                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0) | (fuse_prev ? DRUN_EPILOGUE : 0);
                 op.data = B.put(terms.data(), terms.size() * sizeof(DTerm));
                 op.tab = B.put(off.data(), off.size() * sizeof(uint32_t));
+                if (fuse_prev) ops.back().flags |= BLK_RUN;
             } else {
                 op.k = (int32_t)run.size();
                 op.data = B.put(run.data(), run.size() * sizeof(DSub));

@@ -85,6 +85,81 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
     return w;
 }
 
+// ------------------------------------------------------------ phase angles
+// Long runs: every term adds its angle (a fixed-point fraction of a turn,
+// so sums wrap exactly modulo a full turn) to the elements it matches; each
+// element then takes one factor exp(2 pi i acc / 2^bits), or, when every
+// term is a factor of -1, one sign flip.  complex64 keeps 32-bit turns (each
+// term's angle rounded to 2^-32 turns by the planner), complex128 64-bit.
+template <typename R> struct Turn;
+template <> struct Turn<float> { using T = uint32_t; };
+template <> struct Turn<double> { using T = uint64_t; };
+
+// (cos, sin) of 2 pi t / 2^32: the quadrant from the top two bits, the angle
+// inside it folded to [0, pi/4] (sin and cos exchanged past pi/4), then the
+// Taylor series of sin and cos at 0 (truncation below 2e-10 on [0, pi/4]).
+__device__ __forceinline__ void cis_turns(uint32_t t, float& c, float& s) {
+    const uint32_t q = t >> 30;
+    uint32_t f = t & 0x3FFFFFFFu;
+    const bool fold = f > 0x20000000u;
+    f = fold ? 0x40000000u - f : f;
+    const float x = (float)f * 1.4629180792671596e-9f;          // 2 pi / 2^32
+    const float x2 = x * x;
+    const float sn = x * (1.f + x2 * (-1.f / 6 + x2 * (1.f / 120 + x2 * (-1.f / 5040 + x2 * (1.f / 362880)))));
+    const float cs = 1.f + x2 * (-0.5f + x2 * (1.f / 24 + x2 * (-1.f / 720 + x2 * (1.f / 40320 +
+                                                                                  x2 * (-1.f / 3628800)))));
+    const float a = fold ? sn : cs, b = fold ? cs : sn;
+    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
+    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
+}
+
+// The same for 2 pi t / 2^64 in double precision (truncation below 2e-19).
+__device__ __forceinline__ void cis_turns(uint64_t t, double& c, double& s) {
+    const uint32_t q = (uint32_t)(t >> 62);
+    uint64_t f = t & ((1ull << 62) - 1);
+    const bool fold = f > (1ull << 61);
+    f = fold ? (1ull << 62) - f : f;
+    const double x = (double)f * 3.4061215800865545e-19;         // 2 pi / 2^64
+    const double x2 = x * x;
+    const double sn =
+        x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880 +
+        x2 * (-1.0 / 39916800 + x2 * (1.0 / 6227020800.0 + x2 * (-1.0 / 1307674368000.0 +
+        x2 * (1.0 / 355687428096000.0)))))))));
+    const double cs =
+        1.0 + x2 * (-0.5 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320 + x2 * (-1.0 / 3628800 +
+        x2 * (1.0 / 479001600 + x2 * (-1.0 / 87178291200.0 + x2 * (1.0 / 20922789888000.0 +
+        x2 * (-1.0 / 6402373705728000.0)))))))));
+    const double a = fold ? sn : cs, b = fold ? cs : sn;
+    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
+    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
+}
+
+// Each thread's total angle per element code: one sum per group of terms
+// (per set of element bits they require), then subset sums over the element
+// bits, so element code i collects every group S contained in i.
+template <typename TU, int NHB>
+__device__ __forceinline__ void run_angles(TU (&acc)[1 << NHB], const DTerm* __restrict__ terms,
+                                           const uint32_t* __restrict__ grp, uint64_t base, uint32_t t) {
+    constexpr int NE = 1 << NHB;
+#pragma unroll
+    for (int g = 0; g < NE; ++g) {
+        TU a = 0;
+        const uint32_t q1 = grp[g + 1];
+#pragma unroll 1
+        for (uint32_t q = grp[g]; q < q1; ++q) {
+            const DTerm& d = terms[q];
+            if ((base & d.omask) != d.oval) continue;
+            a += (t & d.lmask) == d.lval ? (TU)d.turns : (TU)0;
+        }
+        acc[g] = a;
+    }
+#pragma unroll
+    for (int b = 0; b < NHB; ++b)
+#pragma unroll
+        for (int i = 0; i < NE; ++i)
+            if ((i >> b) & 1) acc[i] += acc[i ^ (1 << b)];
+}
+
 // ---------------------------------------------------------------- blocks
 // The block's real fragments are already in LDS (after the tile; the
 // kernel stages them while the previous op runs); every k-step reads one A
@@ -103,9 +178,20 @@ __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
 // wave-uniform term.
 constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose fragments stay in registers
 
-template <typename R, int K>
+//
+// With RUN (complex64, 13-qubit tiles, 3- and 4-qubit blocks: one column
+// iteration per wave) the diagonal run that follows the block is applied to
+// the outputs before they are stored.  The run's terms are encoded over the
+// epilogue's layout: thread code threadIdx.x (lane l holds column bits 0..3
+// as l % 16 and block bits 1, 2 as l / 16; the wave holds the top column
+// bits) and element code hh | ct << 1 | rb << (1 + log2 CT) (block bit 0,
+// the column tile, block bit 3).
+template <typename R, int K, bool RUN = false>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
-                                           const char* __restrict__ blob, int L) {
+                                           const char* __restrict__ blob, int L_,
+                                           const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
+    static_assert(!RUN || (sizeof(R) == 4 && (K == 16 || K == 32)), "epilogue runs: complex64, k = 3, 4");
+    const int L = RUN ? 13 : L_;
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
@@ -188,6 +274,17 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                 }
             }
         }
+        using TU = typename Turn<R>::T;
+        constexpr int NEC = RUN ? 16 : 1;
+        constexpr int LCT = CT == 8 ? 3 : CT == 4 ? 2 : CT == 2 ? 1 : 0;
+        TU ang[NEC];
+        bool signs = false;
+        if constexpr (RUN) {
+            static_assert(2 * CT * RB == NEC, "epilogue element code");
+            run_angles<TU, 4>(ang, (const DTerm*)(blob + run->data), (const uint32_t*)(blob + run->tab), base,
+                              threadIdx.x);
+            signs = (run->flags & DRUN_SIGNS) != 0;
+        }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             if (!ok[ct]) continue;
@@ -199,7 +296,22 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
                         const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + hh];
-                        *(float2*)(lds + 2 * sl) = make_float2(acc[ct][rb][2 * hh], acc[ct][rb][2 * hh + 1]);
+                        R yr = acc[ct][rb][2 * hh], yi = acc[ct][rb][2 * hh + 1];
+                        if constexpr (RUN) {
+                            const TU a = ang[(hh | ct << 1 | rb << (1 + LCT)) % NEC];
+                            if (signs) {
+                                const R sg = (a >> 31) ? (R)-1 : (R)1;
+                                yr *= sg;
+                                yi *= sg;
+                            } else {
+                                R fr, fi;
+                                cis_turns(a, fr, fi);
+                                const R xr = yr;
+                                yr = fr * xr - fi * yi;
+                                yi = fr * yi + fi * xr;
+                            }
+                        }
+                        *(float2*)(lds + 2 * sl) = make_float2(yr, yi);
                     }
                 } else {
 #pragma unroll
@@ -281,54 +393,6 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
     }
 }
 
-// Long runs: every term adds its angle (a fixed-point fraction of a turn,
-// so sums wrap exactly modulo a full turn) to the elements it matches; each
-// element then takes one factor exp(2 pi i acc / 2^bits), or, when every
-// term is a factor of -1, one sign flip.  complex64 keeps 32-bit turns (each
-// term's angle rounded to 2^-32 turns by the planner), complex128 64-bit.
-template <typename R> struct Turn;
-template <> struct Turn<float> { using T = uint32_t; };
-template <> struct Turn<double> { using T = uint64_t; };
-
-// (cos, sin) of 2 pi t / 2^32: the quadrant from the top two bits, the angle
-// inside it folded to [0, pi/4] (sin and cos exchanged past pi/4), then the
-// Taylor series of sin and cos at 0 (truncation below 2e-10 on [0, pi/4]).
-__device__ __forceinline__ void cis_turns(uint32_t t, float& c, float& s) {
-    const uint32_t q = t >> 30;
-    uint32_t f = t & 0x3FFFFFFFu;
-    const bool fold = f > 0x20000000u;
-    f = fold ? 0x40000000u - f : f;
-    const float x = (float)f * 1.4629180792671596e-9f;          // 2 pi / 2^32
-    const float x2 = x * x;
-    const float sn = x * (1.f + x2 * (-1.f / 6 + x2 * (1.f / 120 + x2 * (-1.f / 5040 + x2 * (1.f / 362880)))));
-    const float cs = 1.f + x2 * (-0.5f + x2 * (1.f / 24 + x2 * (-1.f / 720 + x2 * (1.f / 40320 +
-                                                                                  x2 * (-1.f / 3628800)))));
-    const float a = fold ? sn : cs, b = fold ? cs : sn;
-    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
-    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
-}
-
-// The same for 2 pi t / 2^64 in double precision (truncation below 2e-19).
-__device__ __forceinline__ void cis_turns(uint64_t t, double& c, double& s) {
-    const uint32_t q = (uint32_t)(t >> 62);
-    uint64_t f = t & ((1ull << 62) - 1);
-    const bool fold = f > (1ull << 61);
-    f = fold ? (1ull << 62) - f : f;
-    const double x = (double)f * 3.4061215800865545e-19;         // 2 pi / 2^64
-    const double x2 = x * x;
-    const double sn =
-        x * (1.0 + x2 * (-1.0 / 6 + x2 * (1.0 / 120 + x2 * (-1.0 / 5040 + x2 * (1.0 / 362880 +
-        x2 * (-1.0 / 39916800 + x2 * (1.0 / 6227020800.0 + x2 * (-1.0 / 1307674368000.0 +
-        x2 * (1.0 / 355687428096000.0)))))))));
-    const double cs =
-        1.0 + x2 * (-0.5 + x2 * (1.0 / 24 + x2 * (-1.0 / 720 + x2 * (1.0 / 40320 + x2 * (-1.0 / 3628800 +
-        x2 * (1.0 / 479001600 + x2 * (-1.0 / 87178291200.0 + x2 * (1.0 / 20922789888000.0 +
-        x2 * (-1.0 / 6402373705728000.0)))))))));
-    const double a = fold ? sn : cs, b = fold ? cs : sn;
-    c = q == 0 ? a : q == 1 ? -b : q == 2 ? -a : b;
-    s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
-}
-
 template <typename R, int L>
 __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DTerm* __restrict__ terms,
                                                    const uint32_t* __restrict__ grp, uint64_t base,
@@ -338,27 +402,8 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     constexpr int NHB = L > kLogTileThreads ? L - kLogTileThreads : 0;   // element bits
     constexpr int NE = 1 << NHB;                                          // elements per thread
     const uint32_t t = threadIdx.x;
-    // one sum per group of terms (per set of element bits they require)
     TU acc[NE];
-#pragma unroll
-    for (int g = 0; g < NE; ++g) {
-        TU a = 0;
-        const uint32_t q1 = grp[g + 1];
-#pragma unroll 1
-        for (uint32_t q = grp[g]; q < q1; ++q) {
-            const DTerm& d = terms[q];
-            if ((base & d.omask) != d.oval) continue;
-            a += (t & d.lmask) == d.lval ? (TU)d.turns : (TU)0;
-        }
-        acc[g] = a;
-    }
-    // subset sums over the element bits: element i collects every group S
-    // with S contained in i
-#pragma unroll
-    for (int b = 0; b < NHB; ++b)
-#pragma unroll
-        for (int i = 0; i < NE; ++i)
-            if ((i >> b) & 1) acc[i] += acc[i ^ (1 << b)];
+    run_angles<TU, NHB>(acc, terms, grp, base, t);
     if (t >= nE) return;
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
@@ -452,9 +497,19 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                     }
                 }
             }
+            // a diagonal run right after the block may ride in its epilogue
+            const bool erun = (op.flags & BLK_RUN) != 0;
             switch (op.k) {
-                case 3: tile_block<R, 16>(lds, ldsA, op, blob, L); break;
-                case 4: tile_block<R, 32>(lds, ldsA, op, blob, L); break;
+                case 3:
+                    if constexpr (sizeof(R) == 4 && L == 13)
+                        if (erun) { tile_block<R, 16, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 16>(lds, ldsA, op, blob, L);
+                    break;
+                case 4:
+                    if constexpr (sizeof(R) == 4 && L == 13)
+                        if (erun) { tile_block<R, 32, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 32>(lds, ldsA, op, blob, L);
+                    break;
                 case 5: tile_block<R, 64>(lds, ldsA, op, blob, L); break;
                 case 6: tile_block<R, 128>(lds, ldsA, op, blob, L); break;
                 default: break;
@@ -473,6 +528,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 __syncthreads();
             }
         } else {
+            if (op.flags & DRUN_EPILOGUE) continue;          // applied by the block before it
             if (op.flags & DRUN_TURNS)
                 tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data),
                                          (const uint32_t*)(blob + op.tab), base,

@@ -16,7 +16,12 @@ constexpr size_t kTileLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
 // Diagonal-run flags (TOp::flags).
 enum : int32_t {
     DRUN_TURNS = 1,         // accumulate each element's phase in turns, one factor per element
-    DRUN_SIGNS = 2          // every term is a factor of -1 (with DRUN_TURNS: a sign flip per element)
+    DRUN_SIGNS = 2,         // every term is a factor of -1 (with DRUN_TURNS: a sign flip per element)
+    DRUN_EPILOGUE = 4       // applied by the preceding block's epilogue (its element layout)
+};
+// Block flags (TOp::flags of a TOP_BLOCK).
+enum : int32_t {
+    BLK_RUN = 1             // the next op is a DRUN_EPILOGUE run this block applies to its outputs
 };
 
 struct TOp {
@@ -94,6 +99,9 @@ static_assert(sizeof(DSub) == 64, "DSub is read as four 16-byte words");
 // subset-sum over the element bits gives element i the total of every group
 // S contained in i.  A condition h_j = 0 on an element bit is rewritten as
 // 1 - h_j on the host, so every term's element condition is a set of ones.
+// A DRUN_EPILOGUE run uses the same records over the layout of the block
+// before it instead (thread code threadIdx.x, four element-code bits; the
+// block kernel documents which tile bits those are).
 struct DTerm {
     uint64_t omask, oval;
     uint64_t turns;

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import C128_TOL, U32
+from tests.util import C128_TOL, U32, blocks_and_diagonals, epilogue_runs
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit, qft_then_brick,
                        random_mixed_circuit, random_planner_circuit, random_pauli_sum)
 
@@ -221,4 +221,21 @@ def test_simplified_circuit_on_gpu(dtype):
     err = float(np.max(np.abs(sv.amplitudes() - oracle.simulate(n, gates, init=5))))
     tol = C128_TOL if dtype == "c128" else plan_bound(plan)
     print(f"{dtype}: {len(gates)} -> {ga.n} gates, err {err:.2e} tol {tol:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("n,k_max", [(13, 3), (13, 4), (18, 3), (20, 4)])
+def test_fused_epilogue_runs(n, k_max):
+    """complex64 in 13-qubit tiles: diagonal runs right after a 3- or
+    4-qubit block are applied by that block's epilogue (terms over its
+    output layout, with conditions on outer bits across many tiles)."""
+    gates = blocks_and_diagonals(n, 4300 + n + k_max, layers=20)
+    init = (91 * n) % (1 << n)
+    sv, plan = run_fused(n, gates, "c64", k_max, 13, init)
+    ne = epilogue_runs(plan)
+    want = oracle.simulate(n, gates, init=init)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = plan_bound(plan)
+    print(f"n={n} k={k_max} {plan.stats()} epilogue runs {ne} err={err:.2e} tol={tol:.2e}")
+    assert ne >= 5
     assert err <= tol

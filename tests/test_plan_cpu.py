@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.util import _DSUB, _DTERM, _TOP, blocks_and_diagonals, plan_image
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit,
                        random_mixed_circuit, random_planner_circuit)
 
@@ -191,29 +192,21 @@ def test_plan_flags_rejected():
     assert qvm.STATUS[st] == "QVM_EARG" and not h.value
 
 
-# Device-image records of the tile kernel (layouts in csrc/tile.hpp).
-_PD = np.dtype([("L", "<i4"), ("c", "<i4"), ("nops", "<i4"), ("remap", "<i4"), ("kmax", "<i4"),
-                ("first_block", "<i4"), ("qmask", "<u8"), ("ops", "<u8"), ("ldoff", "<u8"),
-                ("rmhi", "<u8"), ("rmlo", "<u8")])
-_TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"),
-                 ("next_block", "<i4"), ("flags", "<i4"), ("tab", "<u8")])
-_DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
-                  ("oval", "<u8"), ("pr", "<f8"), ("pi", "<f8"), ("turns", "<u8"), ("pad", "<u8")])
-_DTERM = np.dtype([("omask", "<u8"), ("oval", "<u8"), ("turns", "<u8"), ("lmask", "<u4"), ("lval", "<u4")])
-
-
-def plan_image(plan):
-    import ctypes
-    L = qvm.lib()
-    L.qvm_plan_image.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
-                                 ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64),
-                                 ctypes.POINTER(ctypes.c_int32)]
-    nb, pt, npass = ctypes.c_size_t(), ctypes.c_uint64(), ctypes.c_int32()
-    qvm.check(L.qvm_plan_image(plan._h, None, 0, ctypes.byref(nb), ctypes.byref(pt), ctypes.byref(npass)))
-    buf = np.zeros(nb.value, np.uint8)
-    qvm.check(L.qvm_plan_image(plan._h, buf.ctypes.data, nb.value, None, None, None))
-    rec = lambda off, dt, cnt: np.frombuffer(buf[off: off + cnt * dt.itemsize].tobytes(), dt)
-    return rec, rec(pt.value, _PD, npass.value)
+def run_angles(terms, off, t, nhb, wmask):
+    """Angle-path sums: per element code i and thread code t, the total of
+    every term group whose element-bit set is contained in i."""
+    assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) >= 0)
+    acc = np.zeros((1 << nhb, len(t)), np.uint64)
+    for g in range(1 << nhb):
+        for d in terms[off[g]: off[g + 1]]:
+            assert d["oval"] == 0 and d["lmask"] < 512 and d["lval"] & ~d["lmask"] == 0
+            hit = (t & np.uint64(d["lmask"])) == np.uint64(d["lval"])
+            acc[g] = (acc[g] + np.where(hit, d["turns"], np.uint64(0))) & wmask
+    for b in range(nhb):
+        for i in range(1 << nhb):
+            if (i >> b) & 1:
+                acc[i] = (acc[i] + acc[i ^ (1 << b)]) & wmask
+    return acc
 
 
 def emulate_diagonal_pass(plan, n, width):
@@ -240,18 +233,7 @@ def emulate_diagonal_pass(plan, n, width):
             n_turns += 1
             terms = rec(int(op["data"]), _DTERM, int(op["k"]))
             off = rec(int(op["tab"]), np.dtype("<u4"), (1 << nhb) + 1)
-            assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) >= 0)
-            acc = np.zeros((1 << nhb, len(t)), np.uint64)
-            for g in range(1 << nhb):
-                for d in terms[off[g]: off[g + 1]]:
-                    assert d["oval"] == 0 and d["lmask"] < nt and d["lval"] & ~d["lmask"] == 0
-                    hit = (t & np.uint64(d["lmask"])) == np.uint64(d["lval"])
-                    acc[g] = (acc[g] + np.where(hit, d["turns"], np.uint64(0))) & wmask
-            for b in range(nhb):
-                for i in range(1 << nhb):
-                    if (i >> b) & 1:
-                        acc[i] = (acc[i] + acc[i ^ (1 << b)]) & wmask
-            ang = acc.reshape(-1)              # element t + 512 i at i * len(t) + t
+            ang = run_angles(terms, off, t, nhb, wmask).reshape(-1)   # element t + 512 i at i * len(t) + t
             if op["flags"] & 2:
                 phase *= np.where(ang >> np.uint64(width - 1), -1.0, 1.0)
             else:
@@ -290,6 +272,93 @@ def test_angle_path_encoding_reproduces_diagonal(dtype, n):
         want = oracle.apply_gates(psi, n, gl) * 2.0 ** (n / 2)
         tol = 1e-7 if dtype == "c64" else 1e-12
         assert np.max(np.abs(got - want)) < tol, (only_signs, np.max(np.abs(got - want)))
+
+
+def epilogue_elements(lb, k, L=13):
+    """Tile element held as (thread code, element code) by the epilogue of a
+    complex64 k-qubit block (k = 3, 4) in a 13-qubit tile: lane l, wave w,
+    column tile ct, row block rb and register pair hh hold column
+    (CT w + ct) 16 + l % 16 (the tile bits outside the block, ascending) and
+    block row 8 rb + 2 (l / 16) + hh."""
+    CT, LCT = (8, 3) if k == 3 else (4, 2)
+    free = [b for b in range(L) if b not in lb[:k]]
+    out = np.zeros((16, 512), np.int64)
+    for tc in range(512):
+        lane, w = tc & 63, tc >> 6
+        for ic in range(16):
+            hh, ct, rb = ic & 1, (ic >> 1) & (CT - 1), ic >> (1 + LCT)
+            col = (CT * w + ct) * 16 + (lane & 15)
+            row = 8 * rb + 2 * (lane >> 4) + hh
+            e = sum(((col >> m) & 1) << free[m] for m in range(len(free)))
+            e |= sum(((row >> r) & 1) << lb[r] for r in range(k))
+            out[ic, tc] = e
+    return out
+
+
+@pytest.mark.parametrize("k_max", [3, 4])
+def test_epilogue_runs_reproduce_the_circuit(k_max):
+    """Pins the encoding of diagonal runs that a complex64 block applies to
+    its outputs (13-qubit tiles): emulating the single pass op by op from the
+    plan image (blocks as their matrices on their tile bits, runs from their
+    terms over the block epilogue's layout or the standalone layout) gives
+    the oracle's state of the whole circuit."""
+    n = 13
+    rng = np.random.Generator(np.random.PCG64(4100 + k_max))
+    gates = blocks_and_diagonals(n, 4100 + k_max)
+    plan = qvm.Plan(gates, n, "c64", k_max=k_max, tile_qubits=n)
+    rec, passes = plan_image(plan)
+    assert len(passes) == 1 and passes[0]["remap"] == 0
+    pd = passes[0]
+    c = int(pd["c"])
+    ldoff = rec(int(pd["ldoff"]), np.dtype("<u8"), 1 << (n - c))
+    e = np.arange(1 << n, dtype=np.uint64)
+    phys = ((e & np.uint64((1 << c) - 1)) | ldoff[(e >> np.uint64(c)).astype(np.int64)]).astype(np.int64)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    tile = psi0[phys].copy()
+    wmask = np.uint64(0xFFFFFFFF)
+    t = np.arange(512, dtype=np.uint64)
+    nb, n_epi, prev = 0, 0, None
+    for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
+        if op["type"] == 1:
+            blk = plan.block(nb)
+            nb += 1
+            lb = [int(v) for v in op["lb"][: int(op["k"])]]
+            assert blk["k"] == op["k"]
+            oracle.apply_matrix(tile, n, blk["matrix"], lb)
+            prev = (op, lb)
+            continue
+        if op["flags"] & 1:
+            epi = bool(op["flags"] & 4)
+            nhb = 4
+            terms = rec(int(op["data"]), _DTERM, int(op["k"]))
+            off = rec(int(op["tab"]), np.dtype("<u4"), (1 << nhb) + 1)
+            ang = run_angles(terms, off, t, nhb, wmask)
+            if epi:
+                n_epi += 1
+                assert prev is not None and prev[0]["flags"] & 1
+                where = epilogue_elements(prev[1], int(prev[0]["k"]))
+            else:
+                where = (np.arange(16)[:, None] * 512 + np.arange(512)[None, :])
+            if op["flags"] & 2:
+                f = np.where(ang >> np.uint64(31), -1.0, 1.0)
+            else:
+                f = np.exp(2j * np.pi * (ang.astype(np.float64) / 2.0 ** 32))
+            fac = np.zeros(1 << n, np.complex128)
+            fac[where.reshape(-1)] = f.reshape(-1)
+            assert np.all(fac != 0)           # every element gets exactly one factor
+            tile *= fac
+        else:
+            for d in rec(int(op["data"]), _DSUB, int(op["k"])):
+                hit = (e & np.uint64(d["lmask"])) == np.uint64(d["lval"])
+                f = -1.0 if d["neg"] else d["pr"] + 1j * d["pi"]
+                tile = np.where(hit, tile * f, tile)
+        prev = None
+    assert nb == plan.stats()["blocks"] and n_epi >= 1
+    got = np.zeros(1 << n, np.complex128)
+    got[phys] = tile
+    want = oracle.apply_gates(psi0.copy(), n, gates)
+    assert np.max(np.abs(got - want)) < 1e-7
 
 
 @pytest.mark.parametrize("dtype,c", [("c64", 4), ("c128", 3)])

@@ -35,3 +35,57 @@ def header_functions():
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
             names += re.findall(r"\b(qvm_[a-z0-9_]+)\s*\(", txt)
     return sorted(set(names))
+
+
+# Device-image records of the tile kernel (layouts in csrc/tile.hpp).
+_PD = np.dtype([("L", "<i4"), ("c", "<i4"), ("nops", "<i4"), ("remap", "<i4"), ("kmax", "<i4"),
+                ("first_block", "<i4"), ("qmask", "<u8"), ("ops", "<u8"), ("ldoff", "<u8"),
+                ("rmhi", "<u8"), ("rmlo", "<u8")])
+_TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"),
+                 ("next_block", "<i4"), ("flags", "<i4"), ("tab", "<u8")])
+_DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
+                  ("oval", "<u8"), ("pr", "<f8"), ("pi", "<f8"), ("turns", "<u8"), ("pad", "<u8")])
+_DTERM = np.dtype([("omask", "<u8"), ("oval", "<u8"), ("turns", "<u8"), ("lmask", "<u4"), ("lval", "<u4")])
+
+
+def plan_image(plan):
+    """(record reader, pass descriptors) of a plan's device image."""
+    import ctypes
+    from paper_2212_14201_amd import qvm
+    L = qvm.lib()
+    L.qvm_plan_image.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_int32)]
+    nb, pt, npass = ctypes.c_size_t(), ctypes.c_uint64(), ctypes.c_int32()
+    qvm.check(L.qvm_plan_image(plan._h, None, 0, ctypes.byref(nb), ctypes.byref(pt), ctypes.byref(npass)))
+    buf = np.zeros(nb.value, np.uint8)
+    qvm.check(L.qvm_plan_image(plan._h, buf.ctypes.data, nb.value, None, None, None))
+    rec = lambda off, dt, cnt: np.frombuffer(buf[off: off + cnt * dt.itemsize].tobytes(), dt)
+    return rec, rec(pt.value, _PD, npass.value)
+
+
+def epilogue_runs(plan):
+    """Diagonal runs of a plan that ride in a block's epilogue."""
+    rec, passes = plan_image(plan)
+    return sum(int(op["flags"]) & 4 != 0 for pd in passes
+               for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])) if op["type"] == 2)
+
+
+def blocks_and_diagonals(n, seed, layers=14):
+    """Layers of three dense gates (H, RX, CNOT) each followed by 2..8
+    diagonal gates (RZ, CZ, controlled phase, RZZ, T) on random qubits: the
+    diagonal runs land right after blocks."""
+    from workloads import Gate
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = []
+    for _ in range(layers):
+        for _ in range(3):
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            th = float(rng.uniform(0, 2 * np.pi))
+            gates.append([Gate("h", (a,)), Gate("rx", (a,), (), (th,)), Gate("x", (a,), (b,))][int(rng.integers(0, 3))])
+        for _ in range(int(rng.integers(2, 9))):
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            th = float(rng.uniform(0, 2 * np.pi))
+            gates.append([Gate("rz", (a,), (), (th,)), Gate("z", (a,), (b,)), Gate("p", (a,), (b,), (th,)),
+                          Gate("rzz", (a, b), (), (th,)), Gate("t", (a,))][int(rng.integers(0, 5))])
+    return gates
