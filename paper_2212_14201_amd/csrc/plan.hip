@@ -437,16 +437,17 @@ std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt)
         return e;
     };
     const BlockTabLayout lay(L, k);
+    const uint32_t es = dt == QVM_C64 ? 8u : 16u;     // bytes per amplitude
     std::vector<uint32_t> t((size_t)lay.words(), 0u);
-    for (int ti = 0; ti < lay.ntile; ++ti) t[lay.col() + ti] = tile_swizzle(deposit(16u * ti));
-    for (int i = 0; i < lay.nb; ++i) t[lay.brow() + i] = tile_swizzle(rows(4 * i));
+    for (int ti = 0; ti < lay.ntile; ++ti) t[lay.col() + ti] = es * tile_swizzle(deposit(16u * ti));
+    for (int i = 0; i < lay.nb; ++i) t[lay.brow() + i] = es * tile_swizzle(rows(4 * i));
     for (int rb = 0; rb < lay.ne / 4; ++rb)
         for (int r = 0; r < 4; ++r) {
             // complex64: registers (2h, 2h+1) hold output row 8 rb + h (plus
             // the lane's 2 (l / 16)); complex128: register r holds row
             // 8 rb + 2 r (plus the lane's (l / 16) / 2)
             const int j = dt == QVM_C64 ? (r < 2 ? 8 * rb + r : -1) : 8 * rb + 2 * r;
-            t[lay.erow() + 4 * rb + r] = j < 0 ? 0u : tile_swizzle(rows(j));
+            t[lay.erow() + 4 * rb + r] = j < 0 ? 0u : es * tile_swizzle(rows(j));
         }
     return t;
 }

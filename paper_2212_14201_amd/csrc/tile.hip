@@ -147,9 +147,11 @@ __device__ __forceinline__ void run_angles(TU (&acc)[1 << NHB], const DTerm* __r
         const uint32_t q1 = grp[g + 1];
 #pragma unroll 1
         for (uint32_t q = grp[g]; q < q1; ++q) {
+            // branch-free (every field always used), so the whole record
+            // is fetched by one scalar load
             const DTerm& d = terms[q];
-            if ((base & d.omask) != d.oval) continue;
-            a += (t & d.lmask) == d.lval ? (TU)d.turns : (TU)0;
+            const TU on = (TU)(((base & d.omask) == d.oval) & ((t & d.lmask) == d.lval));
+            a += (TU)d.turns & ((TU)0 - on);
         }
         acc[g] = a;
     }
@@ -221,17 +223,20 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     const int g = lane >> 4;
     // The slots are linear in the bits they are built from, so each address
     // is a wave-uniform part from the block's table (scalar loads) XOR a
-    // per-lane part computed once here.
+    // per-lane part computed once here, all as byte offsets from the tile's
+    // start (LDS address 0), so an access takes one XOR and no add.
+    constexpr uint32_t ES = 2 * sizeof(R);     // bytes per amplitude
+    char* __restrict__ tb = (char*)lds;
     const BlockTabLayout lay(L, k);
     const uint32_t* __restrict__ tab = (const uint32_t*)(blob + op.tab);
     // B operand: complex input row 4 t + g; the lane's share is rows(g)
-    const uint32_t swg = sw(scat(g));
+    const uint32_t swg = ES * sw(scat(g));
     // epilogue: the lane's share of the output row index
     const int jlane = TT<R>::out_row(g, 0) >> 1;
     const int plane = TT<R>::out_row(g, 0) & 1;
-    const uint32_t swo = sw(scat(jlane));
+    const uint32_t swo = ES * sw(scat(jlane));
     // the lane's column inside a column tile
-    const uint32_t swl = sw(dep32((uint32_t)(lane & 15), bmask));
+    const uint32_t swl = ES * sw(dep32((uint32_t)(lane & 15), bmask));
     const R* __restrict__ Arow = ldsA + lane;
     // small blocks keep their A fragments in registers for the whole block
     // (the epilogue's LDS writes would otherwise force a re-read per column
@@ -262,7 +267,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
             const uint32_t st = tab[lay.brow() + t] ^ swg;
             V2 b[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? *(const V2*)(lds + 2 * (swe[ct] ^ st)) : V2{0, 0};
+            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? *(const V2*)(tb + (swe[ct] ^ st)) : V2{0, 0};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -311,13 +316,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                                 yi = fr * yi + fi * xr;
                             }
                         }
-                        *(float2*)(lds + 2 * sl) = make_float2(yr, yi);
+                        *(float2*)(tb + sl) = make_float2(yr, yi);
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + r];
-                        lds[2 * sl + plane] = acc[ct][rb][r];
+                        *(R*)(tb + (sl | (uint32_t)plane * sizeof(R))) = acc[ct][rb][r];
                     }
                 }
             }
@@ -430,10 +435,11 @@ template <typename R, int L>
 __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
     extern __shared__ __align__(16) char smem[];
-    // LDS: the widest block's fragments first (their reads then take
-    // constant offsets from a per-lane base), the tile after them
-    R* ldsA = (R*)smem;
-    R* lds = ldsA + (pd.kmax >= 3 ? 4u << (2 * pd.kmax) : 0u);
+    // LDS: the tile first (at address 0, so tile addresses need no base),
+    // the widest block's fragments after it (their reads take constant
+    // offsets from a per-lane base)
+    R* lds = (R*)smem;
+    R* ldsA = lds + (2u << L);
     constexpr int EP = TT<R>::EP;
     constexpr int C = TT<R>::C < L ? TT<R>::C : L;          // low bits in every tile
     constexpr uint32_t NP = (1u << L) / EP;                  // 16-byte pieces per tile

@@ -43,9 +43,11 @@ __host__ __device__ inline uint32_t tile_swizzle(uint32_t e) {
     return e ^ ((((e >> 4) ^ (e >> 8)) & 7u) << 1);
 }
 
-// Address table of a block op (uint32 words, LDS slots before the complex
-// stride): the wave-uniform parts of the block's LDS addresses, so that the
-// kernel forms each address with one XOR per access.
+// Address table of a block op (uint32 words, byte offsets into the tile:
+// LDS slot times the bytes of one complex amplitude; the tile sits at the
+// start of LDS): the wave-uniform parts of the block's LDS addresses, so
+// that the kernel forms each address with one XOR per access (byte offsets
+// of slots are linear over GF(2) as well).
 //   col[ti], ti < ntile = ceil(2^(L-k) / 16): slot(deposit(16 ti)) over the
 //            tile bits outside the block (the column tile's base)
 //   brow[t], t < K/8:  slot(rows(4 t)), the input rows of k-step pair t
