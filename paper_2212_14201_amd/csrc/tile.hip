@@ -134,6 +134,15 @@ __device__ __forceinline__ void cis_turns(uint64_t t, double& c, double& s) {
     s = q == 0 ? b : q == 1 ? a : q == 2 ? -b : -a;
 }
 
+// x negated when the top bit of the accumulated angle a is set (a half
+// turn): a sign-bit flip, the same result as a multiplication by -1.
+__device__ __forceinline__ float flip_if(float x, uint32_t a) {
+    return __uint_as_float(__float_as_uint(x) ^ (a & 0x80000000u));
+}
+__device__ __forceinline__ double flip_if(double x, uint64_t a) {
+    return __longlong_as_double((long long)((unsigned long long)__double_as_longlong(x) ^ (a & 0x8000000000000000ull)));
+}
+
 // Each thread's total angle per element code: one sum per group of terms
 // (per set of element bits they require), then subset sums over the element
 // bits, so element code i collects every group S contained in i.
@@ -305,9 +314,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                         if constexpr (RUN) {
                             const TU a = ang[(hh | ct << 1 | rb << (1 + LCT)) % NEC];
                             if (signs) {
-                                const R sg = (a >> 31) ? (R)-1 : (R)1;
-                                yr *= sg;
-                                yi *= sg;
+                                yr = flip_if(yr, a);
+                                yi = flip_if(yi, a);
                             } else {
                                 R fr, fi;
                                 cis_turns(a, fr, fi);
@@ -416,9 +424,8 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
         const R xr = lds[e], xi = lds[e + 1];
         if (signs) {
             // the accumulated angle is 0 or a half turn
-            const R sg = (acc[i] >> (8 * sizeof(TU) - 1)) ? (R)-1 : (R)1;
-            lds[e] = sg * xr;
-            lds[e + 1] = sg * xi;
+            lds[e] = flip_if(xr, acc[i]);
+            lds[e + 1] = flip_if(xi, acc[i]);
         } else {
             R fr, fi;
             cis_turns(acc[i], fr, fi);
