@@ -198,16 +198,13 @@ class LearnedPlanner:
     def choose(self, ga, n, dtype="c64"):
         """Returns (candidate, plan, predicted ms) with the smallest prediction.
 
-        The candidates are planned on host threads (the library's planner is
-        reentrant and ctypes releases the GIL) and all their passes are
-        scored in one MLP forward.  Tile candidates are built in full right
-        away (their block matrices and device image cost little next to the
-        schedule, and the winner is almost always one of them); the others
-        are planned for scoring only (no block matrices or device image) and
-        built in full only if one of them wins."""
+        The candidates are planned for scoring only (no block matrices or
+        device image) on host threads (the library's planner is reentrant and
+        ctypes releases the GIL), all their passes are scored in one MLP
+        forward, and only the winner is then built in full."""
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max_workers=min(len(CANDIDATES), os.cpu_count() or 1)) as ex:
-            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=c[0] == "tile"), CANDIDATES))
+            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), CANDIDATES))
         live = [(c, p) for c, p in zip(CANDIDATES, plans) if p is not None]
         feats = [plan_features(p) for _, p in live]
         rows = np.concatenate(feats)
@@ -221,10 +218,7 @@ class LearnedPlanner:
                 o += len(f)
                 if best is None or pred < best[1]:
                     best = (c, pred)
-        chosen = dict(live)[best[0]]
-        if best[0][0] != "tile":
-            chosen = build_plan(ga, n, dtype, best[0])
-        return best[0], chosen, best[1]
+        return best[0], build_plan(ga, n, dtype, best[0]), best[1]
 
     def save(self, path):
         extra = {"mu": self.mu, "sd": self.sd}
