@@ -239,3 +239,19 @@ def test_fused_epilogue_runs(n, k_max):
     print(f"n={n} k={k_max} {plan.stats()} epilogue runs {ne} err={err:.2e} tol={tol:.2e}")
     assert ne >= 5
     assert err <= tol
+
+
+@pytest.mark.parametrize("n,k_max", [(13, 3), (19, 4)])
+def test_fused_epilogue_sign_runs(n, k_max):
+    """Runs of CZ and Z gates only: the block epilogues flip signs (the sign
+    bit of each output) instead of taking a phase factor."""
+    gates = blocks_and_diagonals(n, 4400 + n + k_max, layers=20, signs_only=True)
+    init = (57 * n) % (1 << n)
+    sv, plan = run_fused(n, gates, "c64", k_max, 13, init)
+    ns = epilogue_runs(plan, signs=True)
+    want = oracle.simulate(n, gates, init=init)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = plan_bound(plan)
+    print(f"n={n} k={k_max} {plan.stats()} epilogue sign runs {ns} err={err:.2e} tol={tol:.2e}")
+    assert ns >= 5
+    assert err <= tol

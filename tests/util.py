@@ -64,17 +64,19 @@ def plan_image(plan):
     return rec, rec(pt.value, _PD, npass.value)
 
 
-def epilogue_runs(plan):
-    """Diagonal runs of a plan that ride in a block's epilogue."""
+def epilogue_runs(plan, signs=False):
+    """Diagonal runs of a plan that ride in a block's epilogue (with signs:
+    only those whose terms are all factors of -1)."""
     rec, passes = plan_image(plan)
-    return sum(int(op["flags"]) & 4 != 0 for pd in passes
+    want = 4 | (2 if signs else 0)
+    return sum(int(op["flags"]) & want == want for pd in passes
                for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])) if op["type"] == 2)
 
 
-def blocks_and_diagonals(n, seed, layers=14):
+def blocks_and_diagonals(n, seed, layers=14, signs_only=False):
     """Layers of three dense gates (H, RX, CNOT) each followed by 2..8
-    diagonal gates (RZ, CZ, controlled phase, RZZ, T) on random qubits: the
-    diagonal runs land right after blocks."""
+    diagonal gates (RZ, CZ, controlled phase, RZZ, T; with signs_only CZ and
+    Z only) on random qubits: the diagonal runs land right after blocks."""
     from workloads import Gate
     rng = np.random.Generator(np.random.PCG64(seed))
     gates = []
@@ -86,6 +88,9 @@ def blocks_and_diagonals(n, seed, layers=14):
         for _ in range(int(rng.integers(2, 9))):
             a, b = (int(v) for v in rng.choice(n, 2, replace=False))
             th = float(rng.uniform(0, 2 * np.pi))
+            if signs_only:
+                gates.append([Gate("z", (a,), (b,)), Gate("z", (a,))][int(rng.integers(0, 2))])
+                continue
             gates.append([Gate("rz", (a,), (), (th,)), Gate("z", (a,), (b,)), Gate("p", (a,), (b,), (th,)),
                           Gate("rzz", (a, b), (), (th,)), Gate("t", (a,))][int(rng.integers(0, 5))])
     return gates
