@@ -197,12 +197,13 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // as l % 16 and block bits 1, 2 as l / 16; the wave holds the top column
 // bits) and element code hh | ct << 1 | rb << (1 + log2 CT) (block bit 0,
 // the column tile, block bit 3).
-template <typename R, int K, bool RUN = false>
+template <typename R, int K, int LT, bool RUN = false>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
                                            const char* __restrict__ blob, int L_,
                                            const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
-    static_assert(!RUN || (sizeof(R) == 4 && (K == 16 || K == 32)), "epilogue runs: complex64, k = 3, 4");
-    const int L = RUN ? 13 : L_;
+    static_assert(!RUN || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
+                  "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
+    const int L = RUN ? 13 : L_;              // LT, the kernel's tile width
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
@@ -211,8 +212,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     // a 13-qubit tile for 3-qubit blocks (one iteration, so no column tile's
     // loads wait behind another's stores), 4 for 4-qubit blocks; complex128
     // (twice the accumulator registers): 4 / RB; 1 for wider blocks
-    constexpr int CT = RB >= 4 ? 1 : sizeof(R) == 8 ? 4 / RB : (K == 16 ? 8 : 4);
+    // (at most the wave's share of the tile's column tiles, so that narrower
+    // tiles keep every wave busy)
     constexpr int NW = NT / 64;
+    constexpr int CT0 = RB >= 4 ? 1 : sizeof(R) == 8 ? 4 / RB : (K == 16 ? 8 : 4);
+    constexpr int LK = LT > k ? LT - k : 0;     // column bits (instantiations with LT < k never run)
+    constexpr int NTILE = ((1 << LK) + 15) >> 4;
+    constexpr int CT = CT0 < NTILE / NW ? CT0 : NTILE / NW >= 1 ? NTILE / NW : 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int lb[6];
 #pragma unroll
@@ -515,16 +521,16 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
             switch (op.k) {
                 case 3:
                     if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 16, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
-                    tile_block<R, 16>(lds, ldsA, op, blob, L);
+                        if (erun) { tile_block<R, 16, L, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 16, L>(lds, ldsA, op, blob, L);
                     break;
                 case 4:
                     if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 32, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
-                    tile_block<R, 32>(lds, ldsA, op, blob, L);
+                        if (erun) { tile_block<R, 32, L, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 32, L>(lds, ldsA, op, blob, L);
                     break;
-                case 5: tile_block<R, 64>(lds, ldsA, op, blob, L); break;
-                case 6: tile_block<R, 128>(lds, ldsA, op, blob, L); break;
+                case 5: tile_block<R, 64, L>(lds, ldsA, op, blob, L); break;
+                case 6: tile_block<R, 128, L>(lds, ldsA, op, blob, L); break;
                 default: break;
             }
             __syncthreads();
