@@ -40,7 +40,7 @@ def run_fused(n, gates, dtype, k_max, tile, init=0):
 
 CASES = [  # n, k_max, tile
     (9, 3, 0), (9, 5, 0), (10, 4, 0), (12, 5, 0), (12, 6, 0), (14, 3, 10), (14, 5, 10),
-    (15, 4, 12), (16, 5, 12), (13, 2, 8),
+    (15, 4, 12), (16, 5, 12), (13, 2, 8), (16, 3, 11), (17, 4, 11),
 ]
 
 
