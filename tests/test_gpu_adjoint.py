@@ -26,10 +26,12 @@ def problem(n, layers, terms, seed):
 
 
 def c64_tol(gates, cs):
-    # each gate is one pass of k = 1 in the forward sweep and two (psi and
-    # lambda) in the reverse sweep; lambda carries sum |c|
+    """The stated complex64 gradient bound 2 tau sum|c|: each gate is one
+    pass of k = 1 in the forward sweep and two (psi and lambda) in the
+    reverse sweep, the Pauli sum one pass per term; lambda carries
+    sum |c|."""
     tau = c64_bound([1] * (3 * len(gates)) + [2] * len(cs))
-    return 10 * tau * float(np.sum(np.abs(cs)))
+    return 2 * tau * float(np.sum(np.abs(cs)))
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -96,20 +98,46 @@ def test_autograd_function():
     assert np.allclose(gt.numpy(), w.numpy()[:, None] * g, atol=1e-14)
 
 
-def test_adjoint_20_qubits_batch_64_sampled_against_oracle():
-    """20 qubits, complex64, 16 layers (640 parameters), 40 Pauli terms of
-    weight 2-4, a batch of 64: four batch elements checked in full against
-    the oracle's adjoint."""
+def _batch20(dtype):
     n, B = 20, 64
     gates, P, xs, zs, cs = problem(n, 16, 40, 2001)
     assert P == 640 and len(gates) == 944
     theta = np.random.default_rng(2002).uniform(0, 2 * math.pi, (B, P))
-    prob = adj.AdjointProblem(n, gates, P, xs, zs, cs, B, "c64")
+    prob = adj.AdjointProblem(n, gates, P, xs, zs, cs, B, dtype)
     f, g = prob.run(theta)
+    return n, gates, theta, xs, zs, cs, f, g
+
+
+def test_adjoint_20_qubits_batch_64_sampled_against_oracle():
+    """20 qubits, complex64, 16 layers (640 parameters), 40 Pauli terms of
+    weight 2-4, a batch of 64: four batch elements checked in full against
+    the oracle's adjoint, within the stated bound 2 tau sum|c| and within
+    1e-3 of the largest oracle gradient and of |f| (the stated bound alone
+    is larger than many gradients at this size; the relative bar is what
+    a zero or a wrong-sign output fails)."""
+    n, gates, theta, xs, zs, cs, f, g = _batch20("c64")
     tol = c64_tol(gates, cs)
     for b in (0, 17, 40, 63):
         fo, go = oracle.adjoint(n, gates, theta[b], xs, zs, cs)
+        gmax = float(np.max(np.abs(go)))
         err = float(np.max(np.abs(g[b] - go)))
-        print(f"b={b} f err {abs(f[b] - fo):.2e} grad err {err:.2e} tol {tol:.2e}")
+        ferr = abs(f[b] - fo)
+        print(f"b={b} f {fo:.4e} err {ferr:.2e}; max|g| {gmax:.3e} grad err {err:.2e}; "
+              f"stated bound {tol:.2e}", flush=True)
+        assert ferr <= min(tol, 1e-3 * abs(fo))
+        assert err <= min(tol, 1e-3 * gmax)
+
+
+def test_adjoint_20_qubits_batch_64_complex128():
+    """The same 20-qubit batch in complex128: four elements (other than the
+    complex64 test's) against the oracle's adjoint at 1e-12 (1 + sum|c|),
+    every element's value and gradient finite."""
+    n, gates, theta, xs, zs, cs, f, g = _batch20("c128")
+    tol = 1e-12 * (1 + float(np.sum(np.abs(cs))))
+    assert np.all(np.isfinite(f)) and np.all(np.isfinite(g))
+    for b in (3, 29, 51, 62):
+        fo, go = oracle.adjoint(n, gates, theta[b], xs, zs, cs)
+        err = float(np.max(np.abs(g[b] - go)))
+        print(f"b={b} f err {abs(f[b] - fo):.2e} grad err {err:.2e} tol {tol:.2e}", flush=True)
         assert abs(f[b] - fo) <= tol
         assert err <= tol

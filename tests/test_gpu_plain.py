@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import C128_TOL, c64_bound, gate_ks
+from tests.util import C128_TOL, c64_bound, cdf_eps, cdf_window, gate_ks
 from workloads import (Gate, ghz_circuit, layered_u3_cz, qft_circuit, random_mixed_circuit,
                        random_pauli_sum, w_circuit, uniform_stream)
 
@@ -141,6 +141,11 @@ def test_readouts(dtype):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [3, 9, 14])
 def test_sampling(n, dtype):
+    """complex128: the oracle's sample, a neighbour only where the target
+    lies within 1e-12 of a CDF boundary.  complex64: every sample inside the
+    oracle's CDF window widened by the stated cumulative-probability bound
+    (samples whose target is farther than that from every boundary thereby
+    match exactly)."""
     gates = random_mixed_circuit(n, 60, 30 + n)
     sv = run_gpu(n, gates, dtype)
     psi = oracle.simulate(n, gates)
@@ -148,12 +153,18 @@ def test_sampling(n, dtype):
     got = sv.sample(u).astype(np.int64)
     want, margin = oracle.sample(psi, u)
     want = want.astype(np.int64)
-    # samples whose target sits within the probability error of a CDF
-    # boundary may land in the neighbouring bin; all others must agree
-    t = 1e-12 if dtype == "c128" else (1 << n) * c64_bound(gate_ks(gates)) * 3
-    close = margin <= t
-    assert np.array_equal(got[~close], want[~close])
-    assert np.all(np.abs(got[close] - want[close]) <= 1)
+    if dtype == "c128":
+        close = margin <= 1e-12
+        assert np.array_equal(got[~close], want[~close])
+        assert np.all(np.abs(got[close] - want[close]) <= 1)
+        return
+    eps = cdf_eps(c64_bound(gate_ks(gates)))
+    ok, slack = cdf_window(got, np.cumsum(oracle.probabilities(psi)), u, eps)
+    far = margin > eps
+    print(f"n={n}: eps {eps:.1e}, {int(far.sum())} of {u.size} targets farther than eps from a "
+          f"boundary, {int(np.sum(got != want))} samples differ from the oracle's")
+    assert ok.all()
+    assert np.array_equal(got[far], want[far])
 
 
 def test_renormalize_c64_drift():

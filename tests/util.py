@@ -94,3 +94,25 @@ def blocks_and_diagonals(n, seed, layers=14, signs_only=False):
             gates.append([Gate("rz", (a,), (), (th,)), Gate("z", (a,), (b,)), Gate("p", (a,), (b,), (th,)),
                           Gate("rzz", (a, b), (), (th,)), Gate("t", (a,))][int(rng.integers(0, 5))])
     return gates
+
+
+def cdf_window(samples, cdf, uniforms, eps):
+    """Validity of samples drawn from a perturbed state: with C the FP64
+    cumulative probability of a reference state (C[-1] its total), sample s
+    for uniform u is valid when C(s-1) - eps <= u C[-1] <= C(s) + eps
+    (C(-1) = 0).  If every C of the sampling state is within eps/2 of the
+    reference's, every exact sample of that state passes.  Returns (ok,
+    slack) per sample, slack >= 0 exactly when ok."""
+    s = np.asarray(samples, dtype=np.int64)
+    t = np.asarray(uniforms, dtype=np.float64) * cdf[-1]
+    hi = cdf[s]
+    lo = np.where(s > 0, cdf[np.maximum(s - 1, 0)], 0.0)
+    slack = np.minimum(t - (lo - eps), (hi + eps) - t)
+    return slack >= 0, slack
+
+
+def cdf_eps(tau):
+    """Stated bound on the sampling window for a state with 2-norm error at
+    most tau: sum_i |dp_i| <= 2 tau + tau^2 bounds the error of every
+    cumulative probability, counted once for C(s) and once for the total."""
+    return 2.0 * (2.0 * tau + tau * tau)
