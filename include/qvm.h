@@ -352,7 +352,11 @@ size_t qvm_adjoint_workspace_bytes(int n_qubits, int batch, size_t n_gates);
  * psi_dev and lam_dev each hold batch x 2^n amplitudes of dt (caller-owned,
  * distinct); work_dev at least qvm_adjoint_workspace_bytes.  Outputs on the
  * host: f_out[batch]; grad_out[batch][n_params] (NULL: expectation only).
- * All batch elements run together, one launch per gate; sums in double
+ * All batch elements run together: the gates are split into groups that
+ * target at most 4 (complex64) / 3 (complex128) qubits, and each group is
+ * one launch that keeps those amplitudes of psi and lambda in registers
+ * while it applies (and, in the reverse sweep, differentiates) every gate
+ * of the group, so a group costs one pass over the states.  Sums in double
  * precision.  Synchronous on hip_stream. */
 qvm_status qvm_adjoint_expect_grad(int n_qubits, qvm_dtype dt, int batch,
                                    const qvm_gate* gates, size_t n_gates,

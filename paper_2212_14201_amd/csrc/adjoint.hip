@@ -8,10 +8,11 @@
 //                    psi <- U_l^dagger psi,  lambda <- U_l^dagger lambda.
 // A controlled rotation's generator acts only where its controls are 1.
 //
-// All batch elements advance together: one launch per gate covers the whole
-// batch (blockIdx.y = batch element).  In the reverse sweep a launch reads
-// each amplitude pair of psi and lambda once, accumulates the gradient term
-// in double precision and writes back U^dagger applied to both.
+// All batch elements advance together: one launch per gate group covers the
+// whole batch (blockIdx.y = batch element).  In the reverse sweep a launch
+// reads each amplitude of psi and lambda once, and for every gate of its
+// group, last to first, accumulates the gradient term in double precision
+// and applies U^dagger to both; then writes them back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +29,7 @@ template <typename R> struct AC2;
 template <> struct AC2<float> { using T = float2; };
 template <> struct AC2<double> { using T = double2; };
 
-constexpr int kAdjBlocks = 256;       // blocks per batch element (and reduction partials)
+constexpr int kAdjBlocks = 64;        // blocks per batch element (and reduction partials per row)
 
 __device__ __forceinline__ uint64_t adep(uint64_t w, uint64_t fixed) {
     while (fixed) {
@@ -49,61 +50,152 @@ __device__ double adj_block_sum(double v, double* sh) {
     return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-// One gate on every batch element.  m points at 8 doubles (2x2 complex,
-// row-major) per batch element when per_batch, else at one matrix.
-// mode 0: psi <- M psi.  mode 1: gradient term (gen 1/2/3 = X/Y/Z, 0 = none)
-// from (psi, lam), then psi <- M psi, lam <- M lam (M = U^dagger).
-template <typename R>
-__global__ __launch_bounds__(256) void k_badj(typename AC2<R>::T* __restrict__ psi,
-                                              typename AC2<R>::T* __restrict__ lam,
-                                              uint64_t state_len, uint64_t items, uint64_t tbit,
-                                              uint64_t cmask, const double* __restrict__ m,
-                                              int per_batch, int mode, int gen,
-                                              double* __restrict__ part) {
-    __shared__ double sh[4];
-    const int b = blockIdx.y;
-    auto* P = psi + (size_t)b * state_len;
-    auto* Lm = lam + (size_t)b * state_len;
-    const double* mb = m + (per_batch ? 8 * b : 0);
-    const R m00r = (R)mb[0], m00i = (R)mb[1], m01r = (R)mb[2], m01i = (R)mb[3];
-    const R m10r = (R)mb[4], m10i = (R)mb[5], m11r = (R)mb[6], m11i = (R)mb[7];
-    const uint64_t fixed = tbit | cmask;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+// Gate groups.  The host splits the gate sequence into groups whose gates
+// target at most r qubits (the group's slots; controls may sit on any
+// qubit) and keeps, for every qubit, the program order of the gates that
+// touch it.  A thread owns one item: the 2^r amplitudes of psi (and lambda)
+// that differ only in the slot bits, held in registers for the whole group,
+// so a group costs one read and one write of each state however many gates
+// it holds.  Controls on slot bits are tests of the register index, controls
+// on other bits one test of the item's base index.
+constexpr int kAdjMaxTrain = 64;      // trainable gates per group
+constexpr int kAdjMaxOps = 512;       // gates per group
+constexpr int kAdjThreads = 256;
+
+struct AdjOpDev {
+    uint64_t cout;     // control bits outside the slots
+    int32_t slot;      // target slot
+    int32_t cj;        // control bits among the slots, as a mask over slots
+    int32_t gate;      // row of the matrix tables
+    int32_t gen;       // reverse sweep: 1/2/3 = X/Y/Z generator of a trainable gate, 0 fixed
+    int32_t tix;       // index among the group's trainable gates
+    int32_t pad;
+};
+
+struct AdjGroupArgs {
+    uint64_t tbit[4];  // slot s <-> bit tbit[s] of the amplitude index
+    uint64_t tmask;    // OR of the slot bits
+    int32_t first, count;
+    int32_t n_train, row0;   // trainable gates; gradient row of the first one
+};
+
+// Im( conj(l0) (G p)_0 + conj(l1) (G p)_1 ) in double for G = X, Y, Z.
+template <typename T>
+__device__ __forceinline__ double gen_term(int gen, const T& a0, const T& a1, const T& l0, const T& l1) {
+    const double p0r = a0.x, p0i = a0.y, p1r = a1.x, p1i = a1.y;
+    const double q0r = l0.x, q0i = l0.y, q1r = l1.x, q1i = l1.y;
+    if (gen == 1) return (q0r * p1i - q0i * p1r) + (q1r * p0i - q1i * p0r);   // X: (p1, p0)
+    if (gen == 2) return -(q0r * p1r + q0i * p1i) + (q1r * p0r + q1i * p0i);  // Y: (-i p1, i p0)
+    return (q0r * p0i - q0i * p0r) - (q1r * p1i - q1i * p1r);                  // Z: (p0, -p1)
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ void mul2(const R* m, T& v0, T& v1) {
+    T o0, o1;
+    o0.x = m[0] * v0.x - m[1] * v0.y + m[2] * v1.x - m[3] * v1.y;
+    o0.y = m[0] * v0.y + m[1] * v0.x + m[2] * v1.y + m[3] * v1.x;
+    o1.x = m[4] * v0.x - m[5] * v0.y + m[6] * v1.x - m[7] * v1.y;
+    o1.y = m[4] * v0.y + m[5] * v0.x + m[6] * v1.y + m[7] * v1.x;
+    v0 = o0;
+    v1 = o1;
+}
+
+// One gate on target slot S of the registers (pairs j0, j0 | 2^S).  Returns
+// the thread's gradient term (reverse sweep, trainable gate) before the
+// update.
+template <typename R, int NA, int S, bool REV, typename T>
+__device__ __forceinline__ double adj_slot(T (&a)[NA], T (&l)[NA], const R* m, int cj, bool cok, int gen) {
     double g = 0;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < items; w += stride) {
-        const uint64_t i0 = adep(w, fixed) | cmask, i1 = i0 | tbit;
-        auto a0 = P[i0], a1 = P[i1];
-        if (mode == 1) {
-            auto l0 = Lm[i0], l1 = Lm[i1];
-            // Im( conj(l0) (G psi)_0 + conj(l1) (G psi)_1 ) in double
-            const double p0r = a0.x, p0i = a0.y, p1r = a1.x, p1i = a1.y;
-            const double q0r = l0.x, q0i = l0.y, q1r = l1.x, q1i = l1.y;
-            if (gen == 1) {          // X: (G psi)_0 = psi_1, (G psi)_1 = psi_0
-                g += (q0r * p1i - q0i * p1r) + (q1r * p0i - q1i * p0r);
-            } else if (gen == 2) {   // Y: (G psi)_0 = -i psi_1, (G psi)_1 = i psi_0
-                g += -(q0r * p1r + q0i * p1i) + (q1r * p0r + q1i * p0i);
-            } else if (gen == 3) {   // Z: (G psi)_0 = psi_0, (G psi)_1 = -psi_1
-                g += (q0r * p0i - q0i * p0r) - (q1r * p1i - q1i * p1r);
-            }
-            typename AC2<R>::T o0, o1;
-            o0.x = m00r * l0.x - m00i * l0.y + m01r * l1.x - m01i * l1.y;
-            o0.y = m00r * l0.y + m00i * l0.x + m01r * l1.y + m01i * l1.x;
-            o1.x = m10r * l0.x - m10i * l0.y + m11r * l1.x - m11i * l1.y;
-            o1.y = m10r * l0.y + m10i * l0.x + m11r * l1.y + m11i * l1.x;
-            Lm[i0] = o0;
-            Lm[i1] = o1;
+#pragma unroll
+    for (int j0 = 0; j0 < NA; ++j0) {
+        if (j0 & (1 << S)) continue;
+        constexpr int step = 1 << S;
+        const int j1 = j0 | step;
+        if (!(cok && (j0 & cj) == cj)) continue;
+        if (REV) {
+            if (gen) g += gen_term(gen, a[j0], a[j1], l[j0], l[j1]);
+            mul2<R>(m, l[j0], l[j1]);
         }
-        typename AC2<R>::T o0, o1;
-        o0.x = m00r * a0.x - m00i * a0.y + m01r * a1.x - m01i * a1.y;
-        o0.y = m00r * a0.y + m00i * a0.x + m01r * a1.y + m01i * a1.x;
-        o1.x = m10r * a0.x - m10i * a0.y + m11r * a1.x - m11i * a1.y;
-        o1.y = m10r * a0.y + m10i * a0.x + m11r * a1.y + m11i * a1.x;
-        P[i0] = o0;
-        P[i1] = o1;
+        mul2<R>(m, a[j0], a[j1]);
     }
-    if (mode == 1 && gen) {
-        const double r = adj_block_sum(g, sh);
-        if (threadIdx.x == 0) part[(size_t)b * kAdjBlocks + blockIdx.x] = r;
+    return g;
+}
+
+template <typename R, int r, bool REV>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_group(typename AC2<R>::T* __restrict__ psi,
+                                                           typename AC2<R>::T* __restrict__ lam,
+                                                           uint64_t state_len, uint64_t items,
+                                                           AdjGroupArgs A,
+                                                           const AdjOpDev* __restrict__ ops,
+                                                           const double* __restrict__ mats, int batch,
+                                                           double* __restrict__ part) {
+    using T = typename AC2<R>::T;
+    constexpr int NA = 1 << r;
+    __shared__ double acc[kAdjMaxTrain * (kAdjThreads / 64)];
+    const int b = blockIdx.y;
+    T* P = psi + (size_t)b * state_len;
+    T* Lm = lam + (size_t)b * state_len;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (REV) {
+        for (int i = threadIdx.x; i < A.n_train * (kAdjThreads / 64); i += kAdjThreads) acc[i] = 0;
+        __syncthreads();
+    }
+    uint64_t off[NA];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int s = 0; s < r; ++s)
+            if (j & (1 << s)) o |= A.tbit[s];
+        off[j] = o;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * kAdjThreads;
+    // the loop bound is uniform over the wave, so every lane takes part in
+    // the wave reductions; lanes past the end hold zeros and store nothing
+    for (uint64_t w0 = (uint64_t)blockIdx.x * kAdjThreads + wave * 64; w0 < items; w0 += stride) {
+        const uint64_t w = w0 + lane;
+        const bool act = w < items;
+        const uint64_t base = act ? adep(w, A.tmask) : 0;
+        T a[NA], l[NA];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            a[j] = act ? P[base | off[j]] : T{0, 0};
+            if (REV) l[j] = act ? Lm[base | off[j]] : T{0, 0};
+        }
+        for (int oi = 0; oi < A.count; ++oi) {
+            const AdjOpDev op = ops[A.first + (REV ? A.count - 1 - oi : oi)];
+            const double* md = mats + ((size_t)op.gate * batch + b) * 8;
+            R m[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) m[i] = (R)md[i];
+            const bool cok = act && (base & op.cout) == op.cout;
+            const int gen = REV ? op.gen : 0;
+            double g = 0;
+            switch (op.slot) {
+                case 0: g = adj_slot<R, NA, 0, REV>(a, l, m, op.cj, cok, gen); break;
+                case 1: if constexpr (r > 1) g = adj_slot<R, NA, (r > 1 ? 1 : 0), REV>(a, l, m, op.cj, cok, gen); break;
+                case 2: if constexpr (r > 2) g = adj_slot<R, NA, (r > 2 ? 2 : 0), REV>(a, l, m, op.cj, cok, gen); break;
+                default: if constexpr (r > 3) g = adj_slot<R, NA, (r > 3 ? 3 : 0), REV>(a, l, m, op.cj, cok, gen); break;
+            }
+            if (REV && gen) {
+                for (int o = 32; o > 0; o >>= 1) g += __shfl_down(g, o, 64);
+                if (lane == 0) acc[op.tix * (kAdjThreads / 64) + wave] += g;
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < NA; ++j) {
+                P[base | off[j]] = a[j];
+                if (REV) Lm[base | off[j]] = l[j];
+            }
+        }
+    }
+    if (REV) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < A.n_train; t += kAdjThreads) {
+            const double* v = acc + t * (kAdjThreads / 64);
+            part[((size_t)(A.row0 + t) * batch + b) * kAdjBlocks + blockIdx.x] = (v[0] + v[1]) + (v[2] + v[3]);
+        }
     }
 }
 
@@ -202,9 +294,10 @@ struct AdjGate {
 
 struct AdjLayout {
     size_t mats_off, mats_bytes;     // per-(gate, batch) 2x2 matrices, forward then dagger
-    size_t part_off, part_bytes;     // gradient partials [occ][batch][blocks]
+    size_t ops_off, ops_bytes;       // group op table
+    size_t part_off, part_bytes;     // gradient partials [row][batch][blocks]
     size_t res_off, res_bytes;       // reduced rows
-    size_t fpart_off, total;
+    size_t total;
 };
 
 AdjLayout adj_layout(int batch, size_t n_gates, size_t n_occ) {
@@ -214,6 +307,9 @@ AdjLayout adj_layout(int batch, size_t n_gates, size_t n_occ) {
     L.mats_off = off;
     L.mats_bytes = al(2 * n_gates * (size_t)batch * 8 * sizeof(double));
     off += L.mats_bytes;
+    L.ops_off = off;
+    L.ops_bytes = al((n_gates + 1) * sizeof(AdjOpDev));
+    off += L.ops_bytes;
     L.part_off = off;
     L.part_bytes = al((n_occ + 1) * (size_t)batch * kAdjBlocks * sizeof(double));
     off += L.part_bytes;
@@ -225,6 +321,62 @@ AdjLayout adj_layout(int batch, size_t n_gates, size_t n_occ) {
 }
 
 qvm_status adj_fail(qvm_status st, const std::string& m) { return fail(st, "adjoint: " + m); }
+
+struct HostGroup {
+    AdjGroupArgs args;
+    std::vector<int> gates;          // in program order
+};
+
+// Split the gate sequence into groups of at most r target qubits.  Each
+// group scans the gates not yet placed, in program order, and takes a gate
+// when none of its qubits is held by a gate the scan has passed over (so
+// the order of gates that share a qubit is kept: gates that share no qubit
+// commute) and its target is a slot or a slot is free.  Slots left free are
+// filled with the highest unused qubits, so that the item index runs over
+// the low bits and a wave's loads stay contiguous.
+std::vector<HostGroup> adj_groups(const std::vector<AdjGate>& G, int n, int r) {
+    std::vector<HostGroup> out;
+    std::vector<char> done(G.size(), 0);
+    size_t left = G.size(), first = 0;
+    while (left) {
+        HostGroup h{};
+        int nb = 0, ntrain = 0;
+        int bits[4] = {0, 0, 0, 0};
+        uint64_t blocked = 0, tset = 0;
+        for (size_t i = first; i < G.size(); ++i) {
+            if (done[i]) continue;
+            const uint64_t tb = 1ull << G[i].target;
+            const uint64_t q = tb | G[i].cmask;
+            bool ok = !(q & blocked);
+            if (ok && !(tset & tb) && nb == r) ok = false;
+            if (ok && G[i].pidx >= 0 && ntrain == kAdjMaxTrain) ok = false;
+            if (ok && (int)h.gates.size() == kAdjMaxOps) ok = false;
+            if (!ok) {
+                blocked |= q;
+                continue;
+            }
+            if (!(tset & tb)) {
+                tset |= tb;
+                bits[nb++] = G[i].target;
+            }
+            h.gates.push_back((int)i);
+            done[i] = 1;
+            --left;
+            if (G[i].pidx >= 0) ++ntrain;
+        }
+        while (first < G.size() && done[first]) ++first;
+        for (int q = n - 1; nb < r && q >= 0; --q)
+            if (!(tset >> q & 1)) {
+                tset |= 1ull << q;
+                bits[nb++] = q;
+            }
+        for (int s = 0; s < 4; ++s) h.args.tbit[s] = s < r ? 1ull << bits[s] : 0;
+        h.args.tmask = tset;
+        h.args.n_train = ntrain;
+        out.push_back(std::move(h));
+    }
+    return out;
+}
 
 }  // namespace
 
@@ -270,20 +422,70 @@ static qvm_status adjoint_t(int n, int batch, const std::vector<AdjGate>& G, int
     double* dm = (double*)(work + L.mats_off);
     double* part = (double*)(work + L.part_off);
     double* res = (double*)(work + L.res_off);
+    AdjOpDev* dops = (AdjOpDev*)(work + L.ops_off);
+    // gate groups and their op table; gradient rows follow the group order
+    // complex64 holds 2 x 16 amplitudes per thread (160 VGPRs), complex128
+    // 2 x 8 (four slots would take all 256 and leave one wave per SIMD)
+    const int r = std::min(sizeof(R) == 4 ? 4 : 3, n);
+    std::vector<HostGroup> groups = adj_groups(G, n, r);
+    std::vector<AdjOpDev> optab;
+    std::vector<int> row_gate;        // gradient row (from 1) -> gate
+    row_gate.push_back(-1);
+    for (HostGroup& h : groups) {
+        h.args.first = (int)optab.size();
+        h.args.count = (int)h.gates.size();
+        h.args.row0 = (int)row_gate.size();
+        int tix = 0;
+        for (int gi : h.gates) {
+            AdjOpDev o{};
+            o.gate = gi;
+            o.slot = -1;
+            o.cout = G[gi].cmask;
+            for (int s = 0; s < r; ++s) {
+                if (h.args.tbit[s] == (1ull << G[gi].target)) o.slot = s;
+                if (G[gi].cmask & h.args.tbit[s]) {
+                    o.cj |= 1 << s;
+                    o.cout &= ~h.args.tbit[s];
+                }
+            }
+            o.gen = G[gi].pidx >= 0 ? G[gi].gen : 0;
+            o.tix = G[gi].pidx >= 0 ? tix++ : -1;
+            if (G[gi].pidx >= 0) row_gate.push_back(gi);
+            optab.push_back(o);
+        }
+    }
     QVM_HIP(sv, hipMemcpyAsync(dm, mats.data(), mats.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    if (!optab.empty())
+        QVM_HIP(sv, hipMemcpyAsync(dops, optab.data(), optab.size() * sizeof(AdjOpDev),
+                                   hipMemcpyHostToDevice, stream));
     const dim3 blk(256);
-    // every launch uses exactly kAdjBlocks blocks per batch element, so each
-    // gradient row gets all its partials written (idle threads add zero)
-    auto grid_items = [&](uint64_t) { return (unsigned)kAdjBlocks; };
+    const uint64_t items = 1ull << (n - r);
+    auto launch_group = [&](const HostGroup& h, bool rev) -> qvm_status {
+        const dim3 grid(kAdjBlocks, batch);
+        const double* mt = dm + (rev ? ng : 0) * (size_t)batch * 8;
+#define QVM_ADJ_LAUNCH(RR)                                                                           \
+    if (rev)                                                                                         \
+        hipLaunchKernelGGL((k_adj_group<R, RR, true>), grid, blk, 0, stream, psi, lam, N, items,     \
+                           h.args, dops, mt, batch, part);                                           \
+    else                                                                                             \
+        hipLaunchKernelGGL((k_adj_group<R, RR, false>), grid, blk, 0, stream, psi, lam, N, items,    \
+                           h.args, dops, mt, batch, part);
+        switch (r) {
+            case 1: QVM_ADJ_LAUNCH(1) break;
+            case 2: QVM_ADJ_LAUNCH(2) break;
+            case 3: QVM_ADJ_LAUNCH(3) break;
+            default: QVM_ADJ_LAUNCH(4) break;
+        }
+#undef QVM_ADJ_LAUNCH
+        QVM_LAUNCH_CHECK(sv);
+        return QVM_OK;
+    };
     // forward
     hipLaunchKernelGGL((k_bzero<R>), dim3(1024), blk, 0, stream, psi, N * (uint64_t)batch, N);
     QVM_LAUNCH_CHECK(sv);
-    for (size_t g = 0; g < ng; ++g) {
-        const uint64_t tb = 1ull << G[g].target;
-        const uint64_t items = 1ull << (n - 1 - __builtin_popcountll(G[g].cmask));
-        hipLaunchKernelGGL((k_badj<R>), dim3(grid_items(items), batch), blk, 0, stream, psi, psi, N,
-                           items, tb, G[g].cmask, dm + g * batch * 8, 1, 0, 0, part);
-        QVM_LAUNCH_CHECK(sv);
+    for (const HostGroup& h : groups) {
+        qvm_status st = launch_group(h, false);
+        if (st) return st;
     }
     // lambda = H psi, f = Re <psi|lambda>
     for (int ch = 0; ch < n_term_chunks; ++ch) {
@@ -291,7 +493,7 @@ static qvm_status adjoint_t(int n, int batch, const std::vector<AdjGate>& G, int
                            blk, 0, stream, psi, lam, N, terms[ch], ch > 0 ? 1 : 0);
         QVM_LAUNCH_CHECK(sv);
     }
-    double* fpart = part;   // row block 0 of the partials holds f
+    double* fpart = part;   // row 0 of the partials holds f
     hipLaunchKernelGGL((k_bdot<R>), dim3(kAdjBlocks, batch), blk, 0, stream, psi, lam, N, fpart);
     QVM_LAUNCH_CHECK(sv);
     hipLaunchKernelGGL(k_rows, dim3((batch + 255) / 256), blk, 0, stream, fpart, (uint64_t)batch, res);
@@ -299,32 +501,23 @@ static qvm_status adjoint_t(int n, int batch, const std::vector<AdjGate>& G, int
     QVM_HIP(sv, hipMemcpyAsync(f_out, res, batch * sizeof(double), hipMemcpyDeviceToHost, stream));
     QVM_HIP(sv, hipStreamSynchronize(stream));
     if (!want_grad) return QVM_OK;
-    // reverse sweep: occurrence row o >= 1 for every trainable gate
-    std::vector<int> occ_of(ng, -1);
-    int n_occ = 0;
-    for (size_t g = 0; g < ng; ++g)
-        if (G[g].pidx >= 0) occ_of[g] = ++n_occ;
-    for (size_t gi = ng; gi-- > 0;) {
-        const uint64_t tb = 1ull << G[gi].target;
-        const uint64_t items = 1ull << (n - 1 - __builtin_popcountll(G[gi].cmask));
-        const int gen = G[gi].pidx >= 0 ? G[gi].gen : 0;
-        double* prow = part + (size_t)(occ_of[gi] > 0 ? occ_of[gi] : 0) * batch * kAdjBlocks;
-        const unsigned gx = grid_items(items);
-        hipLaunchKernelGGL((k_badj<R>), dim3(gx, batch), blk, 0, stream, psi, lam, N, items, tb,
-                           G[gi].cmask, dm + (ng + gi) * batch * 8, 1, 1, gen, prow);
+    // reverse sweep: groups in reverse order, gates in reverse inside each
+    for (size_t gi = groups.size(); gi-- > 0;) {
+        qvm_status st = launch_group(groups[gi], true);
+        if (st) return st;
+    }
+    const uint64_t rows = (uint64_t)row_gate.size() * batch;
+    if (row_gate.size() > 1) {
+        hipLaunchKernelGGL(k_rows, dim3((unsigned)((rows + 255) / 256)), blk, 0, stream, part, rows, res);
         QVM_LAUNCH_CHECK(sv);
     }
-    const uint64_t rows = (uint64_t)(n_occ + 1) * batch;
-    hipLaunchKernelGGL(k_rows, dim3((unsigned)((rows + 255) / 256)), blk, 0, stream, part, rows, res);
-    QVM_LAUNCH_CHECK(sv);
-    std::vector<double> r(rows);
-    QVM_HIP(sv, hipMemcpyAsync(r.data(), res, rows * sizeof(double), hipMemcpyDeviceToHost, stream));
+    std::vector<double> rv(rows);
+    QVM_HIP(sv, hipMemcpyAsync(rv.data(), res, rows * sizeof(double), hipMemcpyDeviceToHost, stream));
     QVM_HIP(sv, hipStreamSynchronize(stream));
     std::fill(grad_out, grad_out + (size_t)batch * n_params, 0.0);
-    for (size_t g = 0; g < ng; ++g)
-        if (occ_of[g] > 0)
-            for (int b = 0; b < batch; ++b)
-                grad_out[(size_t)b * n_params + G[g].pidx] += r[(size_t)occ_of[g] * batch + b];
+    for (size_t row = 1; row < row_gate.size(); ++row)
+        for (int b = 0; b < batch; ++b)
+            grad_out[(size_t)b * n_params + G[row_gate[row]].pidx] += rv[row * batch + b];
     return QVM_OK;
 }
 
