@@ -126,6 +126,30 @@ qvm_status qvm_init_basis(qvm_sv* sv, uint64_t index);
  * dense matrices; any number of controls.  Asynchronous. */
 qvm_status qvm_apply(qvm_sv* sv, const qvm_gate* g);
 
+/* Kraus operators of the paper's single-qubit noise channels ("Noise
+ * simulation method"), lowered on the host in double precision:
+ *   QVM_K_DAMPING         [[1, 0], [0, sqrt(1-p)]], [[0, sqrt(p)], [0, 0]]
+ *   QVM_K_DEPHASING       sqrt(1-p) I, sqrt(p) Z (also the phase flip)
+ *   QVM_K_DECOHERENCE     K_a(damping, p1) K_b(dephasing, p2), a, b in {1, 2}
+ *                         (4 operators, a-major), p1 = 1 - exp(-tgate/T1),
+ *                         p2 = (1 - exp(-(tgate/T2 - tgate/(2 T1)))) / 2
+ *   QVM_K_DEPOLARIZING    sqrt(1 - 3p/4) I, sqrt(p)/2 X, sqrt(p)/2 Y, sqrt(p)/2 Z
+ *   QVM_K_BIT_PHASE_FLIP  sqrt(1-p) I, sqrt(p) Y (the printed "bit or phase
+ *                         flip" operator is sqrt(p) Y)
+ *   QVM_K_BIT_FLIP        sqrt(1-p) I, sqrt(p) X
+ *   QVM_K_PHASE_DAMPING   [[1, 0], [0, sqrt(1-p)]], [[0, 0], [0, sqrt(p)]]
+ * Writes *n_ops operators to ops_out (room for QVM_MAX_KRAUS) in the layout
+ * qvm_apply_kraus reads.  p is used by every kind except decoherence, which
+ * uses t1, t2 and tgate.  QVM_ERANGE: p outside [0, 1]; QVM_EARG: unknown
+ * kind, NULL outputs, or decoherence without T1 > 0, T2 > 0, tgate >= 0 and
+ * T2 <= 2 T1 (a negative dephasing rate).  Host-only. */
+typedef enum {
+    QVM_K_DAMPING = 0, QVM_K_DEPHASING = 1, QVM_K_DECOHERENCE = 2, QVM_K_DEPOLARIZING = 3,
+    QVM_K_BIT_PHASE_FLIP = 4, QVM_K_BIT_FLIP = 5, QVM_K_PHASE_DAMPING = 6
+} qvm_channel;
+qvm_status qvm_kraus_ops(qvm_channel kind, double p, double t1, double t2, double tgate,
+                         double* ops_out, int32_t* n_ops);
+
 /* One single-qubit Kraus channel by the trajectory method (paper, "Noise
  * simulation method": noise models given as Kraus operators K_1..K_m; a noisy
  * run unravels each channel into one randomly drawn branch).  ops holds

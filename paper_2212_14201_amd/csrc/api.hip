@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -342,6 +343,60 @@ qvm_status qvm_apply(qvm_sv* sv, const qvm_gate* g) {
     st = gate_matrix(*g, u);
     if (st) return st;
     return launch_op(sv, lower(sv, *g, u));
+}
+
+qvm_status qvm_kraus_ops(qvm_channel kind, double p, double t1, double t2, double tgate,
+                         double* ops_out, int32_t* n_ops) {
+    if (!ops_out || !n_ops) return fail(QVM_EARG, "NULL output");
+    using M2 = std::array<cd, 4>;                     // row-major 2x2
+    const cd I(0, 1);
+    auto pauli = [&](char c, double s) -> M2 {
+        switch (c) {
+            case 'X': return {0, s, s, 0};
+            case 'Y': return {0, -I * s, I * s, 0};
+            case 'Z': return {s, 0, 0, -s};
+            default: return {s, 0, 0, s};
+        }
+    };
+    auto damping = [](double q) -> std::vector<M2> {
+        return {M2{1, 0, 0, std::sqrt(1.0 - q)}, M2{0, std::sqrt(q), 0, 0}};
+    };
+    auto dephasing = [&](double q) -> std::vector<M2> {
+        return {pauli('I', std::sqrt(1.0 - q)), pauli('Z', std::sqrt(q))};
+    };
+    std::vector<M2> ops;
+    if (kind == QVM_K_DECOHERENCE) {
+        if (!(t1 > 0 && t2 > 0 && tgate >= 0))
+            return fail(QVM_EARG, "decoherence needs T1 > 0, T2 > 0, tgate >= 0");
+        if (t2 > 2 * t1) return fail(QVM_EARG, "decoherence needs T2 <= 2 T1 (a non-negative dephasing rate)");
+        const double p1 = 1.0 - std::exp(-tgate / t1);
+        const double p2 = 0.5 * (1.0 - std::exp(-(tgate / t2 - tgate / (2.0 * t1))));
+        for (const M2& a : damping(p1))
+            for (const M2& b : dephasing(p2))
+                ops.push_back(M2{a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
+                                 a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]});
+    } else {
+        if (!(p >= 0.0 && p <= 1.0)) return fail(QVM_ERANGE, "error rate outside [0, 1]");
+        switch (kind) {
+            case QVM_K_DAMPING: ops = damping(p); break;
+            case QVM_K_DEPHASING: ops = dephasing(p); break;
+            case QVM_K_DEPOLARIZING:
+                ops = {pauli('I', std::sqrt(1.0 - 0.75 * p)), pauli('X', 0.5 * std::sqrt(p)),
+                       pauli('Y', 0.5 * std::sqrt(p)), pauli('Z', 0.5 * std::sqrt(p))};
+                break;
+            case QVM_K_BIT_PHASE_FLIP: ops = {pauli('I', std::sqrt(1.0 - p)), pauli('Y', std::sqrt(p))}; break;
+            case QVM_K_BIT_FLIP: ops = {pauli('I', std::sqrt(1.0 - p)), pauli('X', std::sqrt(p))}; break;
+            case QVM_K_PHASE_DAMPING: ops = {M2{1, 0, 0, std::sqrt(1.0 - p)}, M2{0, 0, 0, std::sqrt(p)}}; break;
+            default: return fail(QVM_EARG, "unknown channel kind");
+        }
+    }
+    for (size_t i = 0; i < ops.size(); ++i)
+        for (int e = 0; e < 4; ++e) {
+            ops_out[8 * i + 2 * e] = ops[i][e].real();
+            ops_out[8 * i + 2 * e + 1] = ops[i][e].imag();
+        }
+    *n_ops = (int32_t)ops.size();
+    return QVM_OK;
 }
 
 qvm_status qvm_apply_kraus(qvm_sv* sv, int32_t qubit, int32_t n_ops, const double* ops, double u,

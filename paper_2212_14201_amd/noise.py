@@ -21,67 +21,34 @@ Channels (the paper's equations):
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
-PAULI = {
-    "I": ((1, 0), (0, 1)),
-    "X": ((0, 1), (1, 0)),
-    "Y": ((0, -1j), (1j, 0)),
-    "Z": ((1, 0), (0, -1)),
-}
-
-
-def _scaled(c, name):
-    return c * np.array(PAULI[name], dtype=np.complex128)
-
-
-def _amp_damping(p):
-    k0 = np.diag([1.0, math.sqrt(1.0 - p)]).astype(np.complex128)
-    k1 = np.zeros((2, 2), np.complex128)
-    k1[0, 1] = math.sqrt(p)
-    return [k0, k1]
-
-
-def _phase_flip(p):
-    return [_scaled(math.sqrt(1.0 - p), "I"), _scaled(math.sqrt(p), "Z")]
-
-
-def _check_rate(p):
-    if not 0.0 <= p <= 1.0:
-        raise ValueError(f"error rate {p} outside [0, 1]")
+CHANNELS = {"damping": 0, "dephasing": 1, "phase_flip": 1, "decoherence": 2, "depolarizing": 3,
+            "bit_phase_flip": 4, "bit_flip": 5, "phase_damping": 6}
 
 
 def kraus_ops(kind: str, p: float = 0.0, t1: float = 0.0, t2: float = 0.0,
               tgate: float = 0.0) -> np.ndarray:
-    """Kraus operators of a channel as an (m, 2, 2) complex128 array."""
-    if kind == "decoherence":
-        if not (t1 > 0 and t2 > 0 and tgate >= 0):
-            raise ValueError("decoherence needs T1 > 0, T2 > 0, tgate >= 0")
-        if t2 > 2 * t1:
-            raise ValueError("decoherence needs T2 <= 2 T1 (a non-negative dephasing rate)")
-        p1 = 1.0 - math.exp(-tgate / t1)
-        p2 = 0.5 * (1.0 - math.exp(-(tgate / t2 - tgate / (2.0 * t1))))
-        return np.array([a @ b for a in _amp_damping(p1) for b in _phase_flip(p2)])
-    _check_rate(p)
-    if kind == "damping":
-        ops = _amp_damping(p)
-    elif kind in ("dephasing", "phase_flip"):
-        ops = _phase_flip(p)
-    elif kind == "depolarizing":
-        ops = [_scaled(math.sqrt(1.0 - 0.75 * p), "I")] + \
-              [_scaled(0.5 * math.sqrt(p), P) for P in "XYZ"]
-    elif kind == "bit_phase_flip":
-        ops = [_scaled(math.sqrt(1.0 - p), "I"), _scaled(math.sqrt(p), "Y")]
-    elif kind == "bit_flip":
-        ops = [_scaled(math.sqrt(1.0 - p), "I"), _scaled(math.sqrt(p), "X")]
-    elif kind == "phase_damping":
-        ops = [np.diag([1.0, math.sqrt(1.0 - p)]).astype(np.complex128),
-               np.diag([0.0, math.sqrt(p)]).astype(np.complex128)]
-    else:
+    """Kraus operators of a channel as an (m, 2, 2) complex128 array, lowered
+    by the library (``qvm_kraus_ops``).  ValueError for an unknown kind or
+    invalid rates."""
+    import ctypes
+    from .qvm import QvmError, check, lib
+    if kind not in CHANNELS:
         raise ValueError(f"unknown channel {kind!r}")
-    return np.array(ops)
+    L = lib()
+    L.qvm_kraus_ops.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int32)]
+    L.qvm_kraus_ops.restype = ctypes.c_int
+    buf = np.zeros(16 * 8, dtype=np.float64)
+    m = ctypes.c_int32(0)
+    try:
+        check(L.qvm_kraus_ops(CHANNELS[kind], float(p), float(t1), float(t2), float(tgate),
+                              buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(m)))
+    except QvmError as e:
+        raise ValueError(str(e)) from None
+    return buf[: 8 * m.value].view(np.complex128).reshape(m.value, 2, 2).copy()
 
 
 _CONTROLLED = {("x", 1): "cnot", ("x", 2): "toffoli", ("z", 1): "cz", ("p", 1): "cr"}
