@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(HERE, "liboracle.so")
+# QVM_ORACLE_LIBRARY names another build of the oracle (the host-sanitizer tier)
+_LIB_PATH = os.environ.get("QVM_ORACLE_LIBRARY") or os.path.join(HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -52,6 +53,7 @@ def lib():
                                   _ip, _ip, ctypes.c_int64, _u64p, _u64p, _dp, _dp, _dp]
         L.orc_adjoint.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -62,6 +64,11 @@ def _d(a):
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(t: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(t))
 
 
 def gate_matrix(gate) -> np.ndarray:

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libqvm.so")
+# QVM_LIBRARY names another build of the library (the host-sanitizer tier)
+LIB_PATH = os.environ.get("QVM_LIBRARY") or os.path.join(PKG, "libqvm.so")
 
 QVM_C64, QVM_C128 = 1, 2
 MAX_K = 6
