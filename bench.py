@@ -84,28 +84,206 @@ def stored_traffic(kernel, launches_bytes):
     return rec.get("bytes_per_launch")
 
 
+def host_description():
+    """Host CPU model and core counts of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(n, x, gates, budget_s, plain_bytes_fn):
     """The FP64 oracle on the host cores: a strided sample of the workload's
     gates (every 25th, in order) applied to the 30-qubit state, until the
-    sample or the time budget runs out."""
-    import numpy as np
+    sample or the time budget runs out; once with every thread OpenMP is
+    given, then single-threaded on the next gates of the same sample."""
     import oracle
     sample = gates[::25]
     psi = oracle.basis_state(n, x)
-    done = []
-    t0 = time.perf_counter()
-    for g in sample:
-        oracle.apply_matrix(psi, n, oracle.gate_matrix(g), g.targets, g.controls)
-        done.append(g)
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    all_threads = oracle.max_threads()
+
+    def leg(start, threads, seconds):
+        oracle.set_threads(threads)
+        done = []
+        t0 = time.perf_counter()
+        for g in sample[start:]:
+            oracle.apply_matrix(psi, n, oracle.gate_matrix(g), g.targets, g.controls)
+            done.append(g)
+            if time.perf_counter() - t0 > seconds:
+                break
+        return done, time.perf_counter() - t0
+
+    done, dt = leg(0, all_threads, budget_s * 0.6)
+    one, dt1 = leg(len(done), 1, budget_s * 0.4)
+    oracle.set_threads(all_threads)
     del psi
-    return {"value": len(done) / dt, "unit": "gates/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"{len(done)} gates (every 25th gate of the workload, in order) applied "
-                      f"in complex128 to the {n}-qubit state by the FP64 oracle in {dt:.1f} s",
-            "effective_GBs": plain_bytes_fn(done, n, 16) / dt / 1e9}
+    host = host_description()
+    out = {"value": len(done) / dt, "unit": "gates/s", "cores": all_threads, "kind": "oracle",
+           "sample": f"{len(done)} gates (every 25th gate of the workload, in order) applied "
+                     f"in complex128 to the {n}-qubit state by the FP64 oracle in {dt:.1f} s "
+                     f"on {all_threads} threads",
+           "effective_GBs": plain_bytes_fn(done, n, 16) / dt / 1e9,
+           "single_thread": {"value": len(one) / dt1, "unit": "gates/s", "cores": 1,
+                             "sample": f"the next {len(one)} gates of the same sample in "
+                                       f"{dt1:.1f} s on one thread",
+                             "effective_GBs": plain_bytes_fn(one, n, 16) / dt1 / 1e9}}
+    out.update(host)
+    return out
+
+
+U32 = 2.0 ** -24
+
+
+def golden(name):
+    """Values the FP64 oracle stored for a workload (tests/golden/, written
+    by make_golden.py, which calls only the oracle)."""
+    with open(os.path.join(ROOT, "tests", "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+def tau_of_ks(ks):
+    """Stated complex64 bound on the state's 2-norm error after passes whose
+    matrices are 2^k x 2^k (a diagonal term counts k = 0): (2^k + 4)
+    roundings of size 2^-24 per pass, summed in quadrature, safety factor
+    10."""
+    return 10.0 * math.sqrt(max(sum((1 << k) + 4 for k in ks), 1)) * U32
+
+
+def plan_ks(plan):
+    st = plan.stats()
+    return [plan.block(b)["k"] for b in range(st["blocks"])] + [0] * st["diag_ops"]
+
+
+def errors_vs_oracle(sv, g, n, zz=False):
+    """Errors of a state's results against the oracle's stored values:
+    max-abs and relative 2-norm error of the stored amplitudes (all of them,
+    or those at the stored seeded indices), max-abs error of <Z_q> (and of
+    <Z_q Z_q+1> when stored)."""
+    import numpy as np
+    if "amp_index" in g:
+        idx = np.asarray(g["amp_index"], dtype=np.uint64)
+        got = sv.gather(idx)
+    else:
+        got = sv.amplitudes()
+    want = np.asarray(g["amp_re"]) + 1j * np.asarray(g["amp_im"])
+    out = {"amplitudes_compared": int(want.size),
+           "amp_max_abs": float(np.max(np.abs(got - want))),
+           "amp_rel_2norm": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+           "z_max_abs": float(np.max(np.abs(sv.expect_z_all() - np.asarray(g["z"]))))}
+    if "prob" in g:
+        out["prob_max_abs"] = float(np.max(np.abs(sv.probabilities() - np.asarray(g["prob"]))))
+    if zz and "zz" in g:
+        zx = np.zeros(n - 1, dtype=np.uint64)
+        zm = np.array([(1 << q) | (1 << (q + 1)) for q in range(n - 1)], dtype=np.uint64)
+        v, _ = sv.expect_pauli(zx, zm)
+        out["zz_max_abs"] = float(np.max(np.abs(v - np.asarray(g["zz"]))))
+    return out, got
+
+
+def time_path(torch, sv, init, runner, reps):
+    """Mean run time (s) of `runner()` on a state reset to |init> before each
+    rep (after one untimed rep), from HIP events on the state's stream, plus
+    the host wall time per rep (launch-bound paths)."""
+    sv.init_basis(init)
+    runner()
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sv.init_basis(init)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        runner()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    wall = (time.perf_counter() - t0) / reps
+    return float(sum(times) / len(times)), wall
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def layered_configs(torch, planner, records):
+    """The two layered U3 + CZ workloads, outside the timed steps: 12 qubits,
+    20 layers (launch-bound) and 28 qubits, 40 layers (both dtypes), on the
+    plain path and the fused path, with errors against the oracle's stored
+    values."""
+    import numpy as np
+    from paper_2212_14201_amd import qvm
+    from workloads import SEEDS, config_circuit
+    out = {}
+    for name, reps in (("layered12", 50), ("layered28", 2)):
+        cfg = config_circuit(name)
+        n, gates = cfg["n"], cfg["gates"]
+        ga = qvm.GateArray(gates)
+        g = golden(name)
+        G = len(gates)
+        layers = {"layered12": 20, "layered28": 40}[name]
+        res = {"workload": f"{n} qubits, {layers} layers of U3 + CZ brick from |0..0>, {G} gates",
+               "n_qubits": n, "gates": G}
+        ref = None
+        for path in ("plain_c128", "plain_c64", "fused_c64", "fused_c128"):
+            dtype = path.split("_")[1]
+            progress(f"{name} {path}")
+            sv = qvm.StateVector(n, dtype, init=0)
+            if path.startswith("plain"):
+                runner = lambda: sv.run(ga)
+                extra = {}
+                tau = tau_of_ks([len(gg.targets) for gg in gates])
+            else:
+                if planner is not None and dtype == "c64" and n >= 20:
+                    cand, plan, _ = planner.choose(ga, n, dtype)
+                    setting = "%s, k_max %d, tile %d" % tuple(cand)
+                else:
+                    tile = min(n, 13 if dtype == "c64" else 12)
+                    plan = qvm.Plan(ga, n, dtype, k_max=4, tile_qubits=tile)
+                    setting = f"tile, k_max 4, tile {tile}"
+                runner = lambda: plan.run(sv)
+                st = plan.stats()
+                extra = {"setting": setting, "passes": st["passes"], "blocks": st["blocks"]}
+                tau = tau_of_ks(plan_ks(plan))
+            secs, wall = time_path(torch, sv, 0, runner, reps)
+            err, got = errors_vs_oracle(sv, g, n, zz=True)
+            err["bound"] = 1e-12 if dtype == "c128" else tau
+            if path == "plain_c128":
+                ref = got
+            elif ref is not None:
+                err["amp_max_abs_vs_plain_c128"] = float(np.max(np.abs(got - ref)))
+            rec = {"run_ms": secs * 1e3, "host_ms_per_call": wall * 1e3, "gates_per_s": G / secs,
+                   "error_vs_oracle": err}
+            if path.startswith("plain"):
+                gb = plain_bytes(gates, n, 8 if dtype == "c64" else 16)
+                rec["effective_GBs"] = gb / secs / 1e9
+                rec["frac_of_hbm_peak"] = rec["effective_GBs"] / HBM_PEAK_GBS
+            else:
+                rec["effective_GBs"] = extra["passes"] * 2.0 * (1 << n) * (8 if dtype == "c64" else 16) / secs / 1e9
+            rec.update(extra)
+            if name == "layered28":
+                t0 = time.perf_counter()
+                sv.sample(cfg["uniforms"])
+                rec["sample_1024_ms"] = (time.perf_counter() - t0) * 1e3
+            res[path] = rec
+            records.append({"config": name, "seed": SEEDS[name], "path": path, "dtype": dtype,
+                            "n": n, "gates": G, "passes": extra.get("passes", G), "ms": secs * 1e3,
+                            "GBs": rec["effective_GBs"],
+                            "hbm_frac": rec["effective_GBs"] / HBM_PEAK_GBS,
+                            "error_vs_oracle": err})
+            del sv
+            torch.cuda.empty_cache()
+        out[name] = res
+    return out
 
 
 def copy_bandwidth(torch, nbytes, reps=3):
@@ -211,6 +389,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 comparison path")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 12- and 28-qubit layered workloads")
+    ap.add_argument("--records", default=None,
+                    help="append one JSON record per measured workload and path to this file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -220,7 +402,7 @@ def main():
     import numpy as np
     import torch
     from paper_2212_14201_amd import qvm, profiling
-    from workloads import config_circuit, uniform_stream
+    from workloads import SEEDS, config_circuit, uniform_stream
 
     cfg = config_circuit("qft30")
     n, x, gates = cfg["n"], cfg["init"], cfg["gates"]
@@ -256,6 +438,7 @@ def main():
         r["fused_run_s"] = e0.elapsed_time(e1) / 1e3
         r["fused_e2e_s"] = t2 - t0
         r["stats"] = plan.stats()
+        r["plan"] = plan
         t3 = time.perf_counter()
         r["z"] = fused.expect_z_all()
         r["zz"], _ = fused.expect_pauli(zz_x, zz_z)
@@ -274,14 +457,18 @@ def main():
             r["plain_run_s"] = e2.elapsed_time(e3) / 1e3
         return r
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        progress(f"warmup step {i + 1} done")
     profiling.begin(fused)
     if plain is not None:
         profiling.begin(plain)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = [step() for _ in range(args.steps)]
+    recs = []
+    for i in range(args.steps):
+        recs.append(step())
+        progress(f"step {i + 1} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kstats = {"c64:" + k: v for k, v in profiling.end(fused).items()}
@@ -298,8 +485,8 @@ def main():
         "end_to_end_ms": fused_e2e * 1e3,
         "readout_ms": float(np.mean([r["readout_s"] for r in recs])) * 1e3,
         "gates_per_s": G / fused_run, "gates_per_s_end_to_end": G / fused_e2e,
-        "effective_GBs": plain_bytes(gates, n, 8) / fused_run / 1e9,
-        "pass_GBs": st["passes"] * 2.0 * N * 8 / fused_run / 1e9,
+        "effective_GBs": st["passes"] * 2.0 * N * 8 / fused_run / 1e9,
+        "unfused_equivalent_GBs": plain_bytes(gates, n, 8) / fused_run / 1e9,
         "passes": st["passes"], "blocks": st["blocks"], "blocks_by_k": st["blocks_by_k"],
         "diag_ops": st["diag_ops"], "tile_qubits": st["tile_qubits"],
         "norm_before_renormalize": float(recs[-1]["norm_before"]),
@@ -333,6 +520,18 @@ def main():
         out["speedup_fused_c64_vs_plain_c128"] = prun / fused_run
         z64, z128 = recs[-1]["z"], recs[-1]["z128"]
         out["fused_c64_max_abs_z_error_vs_c128"] = float(np.max(np.abs(z64 - z128)))
+    # errors of both paths' final states against the oracle's stored values
+    # for this workload (amplitudes at 4,096 seeded indices, every <Z_q>)
+    gq = golden("qft30")
+    last_plan = recs[-1]["plan"]
+    err, got64 = errors_vs_oracle(fused, gq, n)
+    err["bound"] = tau_of_ks(plan_ks(last_plan))
+    out["fused_c64"]["error_vs_oracle"] = err
+    if plain is not None:
+        err, got128 = errors_vs_oracle(plain, gq, n)
+        err["bound"] = 1e-12
+        out["plain_c128"]["error_vs_oracle"] = err
+        out["fused_c64"]["error_vs_oracle"]["amp_max_abs_vs_plain_c128"] = float(np.max(np.abs(got64 - got128)))
     # roofline of the kernel class with the largest share of the timed region
     dom_name, dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
     per_launch_s = dom["total_ms"] / dom["launches"] / 1e3
@@ -357,35 +556,53 @@ def main():
                           "GBs": v["bytes"] / (v["total_ms"] / 1e3) / 1e9 if v["total_ms"] else None,
                           "TFLOPs": v["flops"] / (v["total_ms"] / 1e3) / 1e12 if v["total_ms"] else None}
                       for k, v in kstats.items()}
-    # outside the timed steps: the greedy planner's classic setting (one
-    # 5-qubit block per pass) as the baseline of the learned choice
+    # outside the timed steps: the greedy planner without the model, at the
+    # setting it falls back to (4-qubit blocks in 13-qubit tiles) and at the
+    # classic fused-gate setting (one 5-qubit block per pass), beside the
+    # learned choice
     if planner is not None:
         from paper_2212_14201_amd import learned_planner
-        gplan = learned_planner.build_plan(ga, n, "c64", learned_planner.GREEDY)
-        fused.init_basis(x)
-        gplan.run(fused)
-        fused.init_basis(x)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        gplan.run(fused)
-        e1.record()
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1)
-        out["fused_c64"]["greedy_baseline"] = {"setting": "%s, k_max %d, tile %d" % learned_planner.GREEDY,
-                                            "run_ms": gms,
-                                            "learned_speedup": gms / (fused_run * 1e3)}
+        base = {}
+        for label, cand in (("fallback", learned_planner.FALLBACK), ("classic", learned_planner.CLASSIC)):
+            gplan = learned_planner.build_plan(ga, n, "c64", cand)
+            secs, _ = time_path(torch, fused, x, lambda: gplan.run(fused), 2)
+            base[label] = {"setting": "%s, k_max %d, tile %d" % cand, "run_ms": secs * 1e3,
+                           "learned_speedup": secs / fused_run}
+        out["fused_c64"]["greedy_fallback"] = base["fallback"]
+        out["fused_c64"]["greedy_classic"] = base["classic"]
     del fused, plain
     torch.cuda.empty_cache()
     out["hbm_copy_GBs"] = copy_bandwidth(torch, 1 << 33)
     out["fused_c64"]["effective_frac_of_copy"] = out["fused_c64"]["effective_GBs"] / out["hbm_copy_GBs"]
     if "plain_c128" in out:
         out["plain_c128"]["frac_of_copy"] = out["plain_c128"]["effective_GBs"] / out["hbm_copy_GBs"]
+    records = [{"config": "qft30", "seed": SEEDS["qft30"], "path": "fused_c64", "dtype": "c64", "n": n,
+                "gates": G, "passes": st["passes"], "ms": fused_run * 1e3,
+                "GBs": out["fused_c64"]["effective_GBs"],
+                "hbm_frac": out["fused_c64"]["effective_GBs"] / HBM_PEAK_GBS,
+                "mfma_frac": out["fused_c64"].get("tile_frac_of_mfma_peak"),
+                "error_vs_oracle": out["fused_c64"]["error_vs_oracle"]}]
+    if "plain_c128" in out:
+        records.append({"config": "qft30", "seed": SEEDS["qft30"], "path": "plain_c128", "dtype": "c128",
+                        "n": n, "gates": G, "passes": G, "ms": out["plain_c128"]["run_ms"],
+                        "GBs": out["plain_c128"]["effective_GBs"],
+                        "hbm_frac": out["plain_c128"]["frac_of_hbm_peak"],
+                        "error_vs_oracle": out["plain_c128"]["error_vs_oracle"]})
+    if not args.no_configs:
+        out["configs"] = layered_configs(torch, planner, records)
     if not args.no_adjoint:
+        progress("adjoint workload")
         out["adjoint_c64"] = adjoint_measure(torch)
     if not args.no_noise:
+        progress("Kraus-trajectory workload")
         out["noise_c64"] = noise_measure(torch)
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(n, x, gates, args.cpu_seconds, plain_bytes)
+    if args.records:
+        with open(args.records, "a") as fh:
+            for r in records:
+                fh.write(json.dumps(r) + "\n")
     print(json.dumps(out), flush=True)
 
 

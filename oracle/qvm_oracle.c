@@ -54,6 +54,15 @@ int orc_max_threads(void) {
 #endif
 }
 
+/* Thread count of the parallel loops that follow (timing legs only). */
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Gate matrices.  The paper names the gates (H, X, Y, Z, S, T, RX, RY, */
 /* RZ, U3, CNOT, CZ, CR, Toffoli, arbitrary unitaries) but prints no    */

@@ -2,6 +2,8 @@
 
 Calls only the FP64 oracle (oracle/) on the seeded inputs of workloads/:
 
+  layered12.json  12 qubits, 20 layers of U3 + CZ brick from |0..0>: all
+                  4,096 amplitudes, all probabilities, <Z_q> for all q.
   layered28.json  28 qubits, 40 layers of U3 + CZ brick from |0..0>:
                   <Z_q> for all q, <Z_q Z_q+1>, 1,024 samples (with their
                   distance to the nearest CDF boundary), amplitudes at 2,048
@@ -28,6 +30,18 @@ from workloads import config_circuit  # noqa: E402
 
 def sample_indices(n, count, seed):
     return np.random.Generator(np.random.PCG64(seed)).integers(0, 1 << n, count, dtype=np.uint64)
+
+
+def layered12():
+    cfg = config_circuit("layered12")
+    n = cfg["n"]
+    t0 = time.time()
+    psi = oracle.run_packed(n, cfg["gates"], cfg["init"])
+    return {"n": n, "gates": len(cfg["gates"]), "z": oracle.expect_z_all(psi).tolist(),
+            "amp_re": psi.real.tolist(), "amp_im": psi.imag.tolist(),
+            "prob": oracle.probabilities(psi).tolist(),
+            "norm2": oracle.norm2(psi), "oracle_seconds": time.time() - t0,
+            "oracle_threads": oracle.max_threads()}
 
 
 def layered28():
@@ -62,9 +76,9 @@ def qft30():
 
 
 def main():
-    names = sys.argv[1:] or ["layered28", "qft30"]
+    names = sys.argv[1:] or ["layered12", "layered28", "qft30"]
     for name in names:
-        data = {"layered28": layered28, "qft30": qft30}[name]()
+        data = {"layered12": layered12, "layered28": layered28, "qft30": qft30}[name]()
         data["source"] = "FP64 oracle (oracle/qvm_oracle.c) via tests/golden/make_golden.py"
         with open(os.path.join(HERE, name + ".json"), "w") as fh:
             json.dump(data, fh)
