@@ -278,6 +278,19 @@ qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubit
                               int k_max, int tile_qubits, qvm_dtype dt, uint32_t flags,
                               qvm_plan** out);
 
+/* Tile passes with a block width per pass.  In tile mode the gates a pass
+ * takes depend only on the tile width (the block width only changes how
+ * they are fused), so pass i of this plan holds the same gates as pass i of
+ * qvm_plan_greedy at the same tile width with any k_max; here they are
+ * fused into blocks of at most k_of_pass[i] qubits (passes beyond n_k use
+ * k_of_pass[n_k - 1]).  The learned planner picks each pass's width from the
+ * cost model's predictions of the candidate passes.  Validation as in
+ * qvm_plan_greedy with k_max = the narrowest width given; tile_qubits must
+ * hold the widest.  flags as in qvm_plan_greedy_ex. */
+qvm_status qvm_plan_tile_per_pass(const qvm_gate* gates, size_t n_gates, int n_qubits,
+                                  int tile_qubits, const int32_t* k_of_pass, int32_t n_k,
+                                  qvm_dtype dt, uint32_t flags, qvm_plan** out);
+
 /* Plan from an explicit partition: block_of_gate[i] is the block id of gate
  * i; blocks run in ascending id order, one pass each.  QVM_EARG if a block
  * spans more than k_max qubits or the partition breaks the per-qubit gate

@@ -482,7 +482,8 @@ std::vector<R> fragments(const std::vector<cd>& M, int k) {
 }  // namespace
 
 qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int k_max,
-                      int tile_qubits, const uint32_t* partition, qvm_plan** out, bool image) {
+                      int tile_qubits, const uint32_t* partition, qvm_plan** out, bool image,
+                      const int32_t* k_of_pass = nullptr, int n_k_of_pass = 0) {
     if (!out) return fail(QVM_EARG, "NULL out");
     *out = nullptr;
     if (n < 1 || n > QVM_MAX_QUBITS) return fail(QVM_EARG, "n_qubits outside 1..34");
@@ -550,6 +551,11 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
     if (L < n && L <= c)
         return fail(QVM_EARG, "tile_qubits must exceed " + std::to_string(cdef) +
                                   " (the low bits every tile holds) when the state has more qubits");
+    // one workgroup of kTileThreads per tile: the grid must stay below 2^32
+    // threads (at 34 qubits, tiles of at least 12 qubits)
+    if ((uint64_t)kTileThreads << (n - L) > 0xFFFFFFFFull)
+        return fail(QVM_EARG, "tile of " + std::to_string(L) + " qubits too narrow for " + std::to_string(n) +
+                                  " qubits: the pass would launch 2^32 or more threads");
 
     // ---- units for block / partition modes (one pass per block)
     std::vector<int> all(ngw);
@@ -656,8 +662,11 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 if (popc(T) >= L) break;
                 T |= 1ull << w.second;
             }
-            pp.units = fuse(G, taken, n, k_max, T);
-            absorb_diagonals(pp.units, G, k_max, T);
+            // block width of this pass: a pass's gates depend only on the
+            // tile width, so each pass may fuse them with its own k
+            const int kp = k_of_pass ? k_of_pass[std::min((int)P->passes.size(), n_k_of_pass - 1)] : k_max;
+            pp.units = fuse(G, taken, n, kp, T);
+            absorb_diagonals(pp.units, G, kp, T);
         } else {
             // diagonal units ride in the pass of the next block
             while (next_unit < units.size()) {
@@ -1021,6 +1030,28 @@ qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubit
     if (flags & ~(uint32_t)QVM_PLAN_NO_IMAGE) return fail(QVM_EARG, "unknown plan flags");
     return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out,
                       (flags & QVM_PLAN_NO_IMAGE) == 0);
+}
+
+qvm_status qvm_plan_tile_per_pass(const qvm_gate* gates, size_t n_gates, int n_qubits, int tile_qubits,
+                                  const int32_t* k_of_pass, int32_t n_k, qvm_dtype dt, uint32_t flags,
+                                  qvm_plan** out) {
+    if (flags & ~(uint32_t)QVM_PLAN_NO_IMAGE) return fail(QVM_EARG, "unknown plan flags");
+    if (n_k < 1 || !k_of_pass) return fail(QVM_EARG, "empty per-pass block widths");
+    if (tile_qubits == 0) return fail(QVM_EARG, "per-pass block widths need tile passes (tile_qubits > 0)");
+    int kmax = 0, kmin = 7;
+    for (int i = 0; i < n_k; ++i) {
+        kmax = std::max(kmax, (int)k_of_pass[i]);
+        kmin = std::min(kmin, (int)k_of_pass[i]);
+    }
+    if (kmin < 1 || kmax > 6) return fail(QVM_EARG, "per-pass block width outside 1..6");
+    // the tile must hold the widest block (and, in complex128, its fragments)
+    const int Lmax = dt == QVM_C64 ? 13 : (kmax >= 6 ? 11 : 12);
+    if (tile_qubits < std::min(kmax, n_qubits) || tile_qubits > Lmax)
+        return fail(QVM_EARG, "tile_qubits must lie in [widest per-pass block width, 13] (complex64) / "
+                              "[.., 12] (complex128, 11 with a 6-qubit width)");
+    // validation (gate spans, tile width) against the narrowest width used
+    return build_plan(gates, n_gates, n_qubits, dt, kmin, tile_qubits, nullptr, out,
+                      (flags & QVM_PLAN_NO_IMAGE) == 0, k_of_pass, n_k);
 }
 
 qvm_status qvm_plan_from_partition(const qvm_gate* gates, size_t n_gates, const uint32_t* block_of_gate,

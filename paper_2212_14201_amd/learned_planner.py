@@ -43,8 +43,13 @@ NFEAT = 22
 # the trained cost model shipped with the package (complex64 pass timings)
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "costmodel_c64.npz")
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
-              ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13), ("tile", 4, 12), ("tile", 3, 11)]
-GREEDY = ("block", 5, 0)       # fallback and baseline: 5-qubit blocks, one pass each
+              ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13),
+              ("tile", 3, 12), ("tile", 4, 12), ("tile", 5, 12), ("tile", 3, 11)]
+FALLBACK = ("tile", 4, 13)     # the greedy planner's setting when no model is shipped
+CLASSIC = ("block", 5, 0)      # the classic fused-gate simulator: 5-qubit blocks, one pass each
+# tile widths at which the model also picks the block width of every pass
+ADAPTIVE_TILES = (13, 12)
+ADAPTIVE_K = (3, 4, 5)
 TILE_KIND = 6                  # kernel class index of the tile kernel in the profiler
 
 
@@ -64,12 +69,20 @@ def cand_for_dtype(c, dtype):
     return mode, k, tile
 
 
-def build_plan(ga, n, dtype, cand, image=True):
+def build_plan(ga, n, dtype, cand, image=True, k_of_pass=None):
+    """A candidate plan: (mode, k_max, tile) of the greedy planner, or
+    ("adaptive", k, tile) with the per-pass block widths k_of_pass."""
     mode, k, tile = cand_for_dtype(cand, dtype)
     try:
+        if mode == "adaptive":
+            return qvm.Plan(ga, n, dtype, tile_qubits=tile, image=image, k_of_pass=k_of_pass)
         return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile, image=image)
     except qvm.QvmError:
         return None        # e.g. a Toffoli does not fit 2-qubit blocks
+
+
+def cand_name(cand):
+    return "%s-%d-%d" % tuple(cand)
 
 
 def plan_features(plan) -> np.ndarray:
@@ -201,7 +214,13 @@ class LearnedPlanner:
         The candidates are planned for scoring only (no block matrices or
         device image) on host threads (the library's planner is reentrant and
         ctypes releases the GIL), all their passes are scored in one MLP
-        forward, and only the winner is then built in full."""
+        forward, and only the winner is then built in full.  Beside the fixed
+        settings, at each tile width of ADAPTIVE_TILES the model picks every
+        pass's block width: a tile pass takes the same gates whatever its
+        width, so pass i of the fixed-width candidates are alternatives for
+        the same work and the pass with the smallest prediction is taken
+        (candidate ("adaptive", widest k, tile); the widths are in
+        plan.k_of_pass)."""
         from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max_workers=min(len(CANDIDATES), os.cpu_count() or 1)) as ex:
             plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), CANDIDATES))
@@ -209,16 +228,26 @@ class LearnedPlanner:
         feats = [plan_features(p) for _, p in live]
         rows = np.concatenate(feats)
         if len(rows) == 0:                   # nothing to run: every plan is empty
-            best = (live[0][0], 0.0)
-        else:
-            ms = self.predict_pass_ms(rows)
-            best, o = None, 0
-            for (c, _), f in zip(live, feats):
-                pred = float(ms[o:o + len(f)].sum())
-                o += len(f)
-                if best is None or pred < best[1]:
-                    best = (c, pred)
-        return best[0], build_plan(ga, n, dtype, best[0]), best[1]
+            c0 = live[0][0]
+            return c0, build_plan(ga, n, dtype, c0), 0.0
+        ms = self.predict_pass_ms(rows)
+        per, o = {}, 0
+        for (c, _), f in zip(live, feats):
+            per[c] = ms[o:o + len(f)]
+            o += len(f)
+        options = [(float(v.sum()), c, None) for c, v in per.items()]
+        for L in ADAPTIVE_TILES:
+            group = [c for c in per if c[0] == "tile" and cand_for_dtype(c, dtype)[2] == L and c[1] in ADAPTIVE_K]
+            if len(group) < 2 or len({len(per[c]) for c in group}) != 1 or len(per[group[0]]) == 0:
+                continue
+            P = np.stack([per[c] for c in group])
+            pick = P.argmin(axis=0)
+            ks = [group[i][1] for i in pick]
+            options.append((float(P.min(axis=0).sum()), ("adaptive", max(ks), L), ks))
+        pred, cand, ks = min(options, key=lambda t: t[0])
+        plan = build_plan(ga, n, dtype, cand, k_of_pass=ks)
+        plan.k_of_pass = ks
+        return cand, plan, pred
 
     def save(self, path):
         extra = {"mu": self.mu, "sd": self.sd}
@@ -284,12 +313,28 @@ def train(F, T, epochs=60, batch=4096, lr=2e-3, hidden=128, seed=0, device="cuda
 
 
 # ----------------------------------------------------------------- evaluate
-def evaluate(planner, first, count, dtype="c64", all_cands=50, check_amplitudes=8, n_range=(26, 32),
-             g_range=(100, 500), mix=False):
-    """Held-out circuits: measured time of the learned choice against the
-    greedy planner (5-qubit blocks, one pass each), the best fixed setting
-    and, for the first `all_cands` circuits, every candidate.  mix: circuits
-    from the family mixture instead of the random planner workload."""
+def max_abs_vs_c128(fused, plain, chunk=1 << 26):
+    """Max-abs difference of two states over every amplitude (both in the
+    identity layout), in chunks."""
+    import torch
+    n = 1 << fused.n
+    worst = 0.0
+    for o in range(0, n, chunk):
+        m = min(chunk, n - o)
+        a = fused.amps[2 * o: 2 * (o + m)].to(torch.float64)
+        b = plain.amps[2 * o: 2 * (o + m)]
+        d = (a - b).view(m, 2)
+        worst = max(worst, float(torch.sqrt((d * d).sum(dim=1)).max()))
+    return worst
+
+
+def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26, 32),
+             g_range=(100, 500), mix=False, log=True):
+    """Held-out circuits: measured time (best of `reps` runs) of the learned
+    choice and of every fixed candidate setting (the fallback tile-4-13
+    among them), and, with check, the learned plan's whole final state
+    against the plain complex128 path.  mix: circuits from the family
+    mixture instead of the random planner workload."""
     import torch
     from workloads import planner_mix_circuit
     if mix:
@@ -297,71 +342,81 @@ def evaluate(planner, first, count, dtype="c64", all_cands=50, check_amplitudes=
     else:
         jobs = [(planner_circuit(s, n_range, g_range), s) for s in range(first, first + count)]
     jobs.sort(key=lambda j: j[0][0])
-    pool = StatePool()
     recs = []
     t0 = time.time()
+    cur_n, sv = None, None
     for i, ((n, gates), s) in enumerate(jobs):
+        if n != cur_n:
+            sv = None
+            torch.cuda.empty_cache()
+            sv = qvm.StateVector(n, dtype, init=0)
+            cur_n = n
         ga = qvm.GateArray(gates)
+        tp = time.perf_counter()
         cand, plan, pred = planner.choose(ga, n, dtype)
-        sv = pool.get(n, dtype)
-        learned_ms, _ = time_plan(sv, plan)
-        g_plan = build_plan(ga, n, dtype, GREEDY)
-        greedy_ms = time_plan(sv, g_plan)[0] if g_plan is not None else float("nan")
-        rec = {"seed": s, "n": n, "gates": len(gates), "choice": list(cand), "pred_ms": pred,
-               "learned_ms": learned_ms, "greedy_ms": greedy_ms}
-        if s - first < all_cands:
-            allm = {}
-            for c in CANDIDATES:
-                p = build_plan(ga, n, dtype, c)
-                if p is not None:
-                    allm["%s-%d-%d" % c] = time_plan(sv, p)[0]
-            rec["all_ms"] = allm
-        recs.append(rec)
-        if (i + 1) % 20 == 0:
-            print(f"evaluate: {i + 1}/{len(jobs)} circuits, {time.time() - t0:.0f} s", flush=True)
-    # amplitudes of the learned plan against the plain complex128 path
-    checks = []
-    if check_amplitudes:
-        pool = None
-        torch.cuda.empty_cache()
-        for (n, gates), s in sorted(jobs, key=lambda j: j[0][0])[:check_amplitudes]:
-            ga = qvm.GateArray(gates)
-            cand, plan, _ = planner.choose(ga, n, dtype)
-            fused = qvm.StateVector(n, dtype, init=0)
-            plan.run(fused)
+        plan_ms = (time.perf_counter() - tp) * 1e3
+        best = lambda p: min(time_plan(sv, p)[0] for _ in range(reps))
+        rec = {"seed": s, "n": n, "gates": len(gates), "choice": cand_name(cand), "pred_ms": pred,
+               "plan_ms": plan_ms, "learned_ms": best(plan)}
+        if plan.k_of_pass is not None:
+            rec["k_of_pass"] = plan.k_of_pass
+        allm = {}
+        for c in CANDIDATES:
+            p = build_plan(ga, n, dtype, c)
+            if p is not None:
+                allm[cand_name(c)] = best(p)
+        rec["all_ms"] = allm
+        if check:
+            # the learned plan's whole state against the unfused complex128 path
+            sv.init_basis(0)
+            plan.run(sv)
+            sv.reset_layout()
             plain = qvm.StateVector(n, "c128", init=0)
             plain.run(ga)
-            idx = np.random.Generator(np.random.PCG64(s)).integers(0, 1 << n, 4096, dtype=np.uint64)
-            err = float(np.max(np.abs(fused.gather(idx) - plain.gather(idx))))
-            checks.append({"seed": s, "n": n, "choice": list(cand), "max_abs_err_vs_c128": err})
-            del fused, plain
+            rec["max_abs_err_vs_c128"] = max_abs_vs_c128(sv, plain)
+            del plain
             torch.cuda.empty_cache()
-    return recs, checks
+        recs.append(rec)
+        if log and ((i + 1) % 10 == 0 or i + 1 == len(jobs)):
+            print(f"evaluate: {i + 1}/{len(jobs)} circuits, {time.time() - t0:.0f} s", flush=True)
+    return recs
 
 
-def summarize(recs, checks):
-    sp = np.array([r["greedy_ms"] / r["learned_ms"] for r in recs if np.isfinite(r["greedy_ms"])])
-    out = {"circuits": len(recs), "median_speedup_vs_greedy": float(np.median(sp)),
-           "geomean_speedup_vs_greedy": float(np.exp(np.mean(np.log(sp)))),
-           "wins": int(np.sum(sp > 1.0)), "losses": int(np.sum(sp < 1.0)),
-           "learned_total_ms": float(sum(r["learned_ms"] for r in recs)),
-           "greedy_total_ms": float(sum(r["greedy_ms"] for r in recs))}
-    full = [r for r in recs if "all_ms" in r]
-    if full:
-        regret = [r["learned_ms"] / min(r["all_ms"].values()) for r in full]
-        fixed = {}
-        for r in full:
-            for k, v in r["all_ms"].items():
-                fixed.setdefault(k, []).append(v)
-        best_fixed = min(fixed, key=lambda k: sum(fixed[k]))
-        out.update({"all_candidates_measured": len(full),
-                    "learned_over_best_candidate_geomean": float(np.exp(np.mean(np.log(regret)))),
-                    "best_fixed_setting": best_fixed,
-                    "learned_vs_best_fixed_total": float(sum(fixed[best_fixed]) /
-                                                         sum(r["learned_ms"] for r in full))})
-    if checks:
-        out["max_abs_err_vs_c128"] = float(max(c["max_abs_err_vs_c128"] for c in checks))
-        out["amplitude_checks"] = len(checks)
+def _ratios(num, den):
+    r = np.asarray(num, dtype=np.float64) / np.asarray(den, dtype=np.float64)
+    return {"wins": int(np.sum(r > 1.01)), "losses": int(np.sum(r < 0.99)),
+            "ties_within_1pct": int(np.sum((r >= 0.99) & (r <= 1.01))),
+            "median_speedup": float(np.median(r)), "geomean_speedup": float(np.exp(np.mean(np.log(r)))),
+            "min_speedup": float(r.min()), "max_speedup": float(r.max())}
+
+
+def summarize(recs):
+    """Speed-ups of the learned choice (time of the other / learned time):
+    over the fallback setting, over the single fixed setting with the
+    smallest total time on these circuits, over the classic one block per
+    pass, and the learned time over the best candidate of each circuit."""
+    learned = [r["learned_ms"] for r in recs]
+    keys = set.intersection(*(set(r["all_ms"]) for r in recs))
+    best_fixed = min(keys, key=lambda k: sum(r["all_ms"][k] for r in recs))
+    fb, cl = cand_name(FALLBACK), cand_name(CLASSIC)
+    out = {"circuits": len(recs),
+           "choices": {c: sum(r["choice"] == c for r in recs) for c in sorted({r["choice"] for r in recs})},
+           "learned_total_ms": float(sum(learned)),
+           "vs_fallback": dict(setting=fb, total_ms=float(sum(r["all_ms"][fb] for r in recs)),
+                               **_ratios([r["all_ms"][fb] for r in recs], learned)),
+           "vs_best_fixed": dict(setting=best_fixed,
+                                 total_ms=float(sum(r["all_ms"][best_fixed] for r in recs)),
+                                 **_ratios([r["all_ms"][best_fixed] for r in recs], learned)),
+           "learned_over_best_candidate_geomean": float(np.exp(np.mean(np.log(
+               [r["learned_ms"] / min(r["all_ms"].values()) for r in recs])))),
+           "mean_plan_ms": float(np.mean([r["plan_ms"] for r in recs]))}
+    if cl in keys:
+        out["vs_classic"] = dict(setting=cl, **_ratios([r["all_ms"][cl] for r in recs], learned))
+    errs = [r["max_abs_err_vs_c128"] for r in recs if "max_abs_err_vs_c128" in r]
+    if errs:
+        out["amplitude_checks"] = len(errs)
+        out["max_abs_err_vs_c128"] = float(max(errs))
+        out["within_1e-5"] = int(sum(e <= 1e-5 for e in errs))
     return out
 
 
@@ -369,21 +424,25 @@ def explain(planner, n, gates, x=0, dtype="c64", measure=True):
     """Every candidate's predicted (and, if `measure`, measured) time for one
     circuit; returns (choice, rows)."""
     ga = qvm.GateArray(gates)
-    cand, _, pred = planner.choose(ga, n, dtype)
+    cand, chosen, pred = planner.choose(ga, n, dtype)
     rows = []
     sv = qvm.StateVector(n, dtype, init=0) if measure else None
     for c in CANDIDATES:
         p = build_plan(ga, n, dtype, c)
         if p is None:
             continue
-        rows.append({"candidate": "%s-%d-%d" % c, "predicted_ms": planner.predict_plan_ms(p),
+        rows.append({"candidate": cand_name(c), "predicted_ms": planner.predict_plan_ms(p),
                      "measured_ms": time_plan(sv, p, x)[0] if measure else None})
-    return {"choice": "%s-%d-%d" % cand, "predicted_ms": pred}, rows
+    choice = {"choice": cand_name(cand), "predicted_ms": pred,
+              "measured_ms": time_plan(sv, chosen, x)[0] if measure else None}
+    if chosen.k_of_pass is not None:
+        choice["k_of_pass"] = chosen.k_of_pass
+    return choice, rows
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "explain"])
+    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "explain", "summarize"])
     ap.add_argument("--workload", default="qft30", help="explain: a named workload of workloads.config_circuit")
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--count", type=int, default=2000)
@@ -391,7 +450,8 @@ def main():
     ap.add_argument("--data", nargs="+", default=["gpurun_out/planner_train.npz"])
     ap.add_argument("--model", default="gpurun_out/costmodel.npz")
     ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--all-cands", type=int, default=50)
+    ap.add_argument("--no-check", action="store_true", help="evaluate: skip the complex128 comparison")
+    ap.add_argument("--reports", nargs="+", default=[], help="summarize: evaluation reports to merge")
     ap.add_argument("--report", default="gpurun_out/planner_eval.json")
     ap.add_argument("--no-mix", action="store_true", help="collect: the random planner workload only")
     ap.add_argument("--mix", action="store_true", help="evaluate: circuits from the family mixture")
@@ -411,13 +471,18 @@ def main():
         print(json.dumps(choice), flush=True)
         for r in rows:
             print(json.dumps(r), flush=True)
-    else:
+    elif a.cmd == "evaluate":
         planner = LearnedPlanner.load(a.model)
-        recs, checks = evaluate(planner, a.first, a.count, all_cands=a.all_cands, mix=a.mix)
-        summ = summarize(recs, checks)
+        recs = evaluate(planner, a.first, a.count, mix=a.mix, check=not a.no_check)
         with open(a.report, "w") as fh:
-            json.dump({"summary": summ, "records": recs, "checks": checks}, fh)
-        print(json.dumps(summ), flush=True)
+            json.dump({"records": recs}, fh)
+        print(json.dumps(summarize(recs)), flush=True)
+    elif a.cmd == "summarize":
+        recs = []
+        for path in a.reports:
+            with open(path) as fh:
+                recs += json.load(fh)["records"]
+        print(json.dumps(summarize(recs), indent=1), flush=True)
 
 
 if __name__ == "__main__":

@@ -423,6 +423,8 @@ def _declare_plan(L):
                                     ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_vp)]),
         "qvm_plan_from_partition": (st, [_gp, ctypes.c_size_t, _u32p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.POINTER(_vp)]),
+        "qvm_plan_tile_per_pass": (st, [_gp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _i32p,
+                                        ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_vp)]),
         "qvm_plan_info": (st, [_vp, ctypes.POINTER(QvmPlanStats)]),
         "qvm_plan_block": (st, [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, _dp]),
         "qvm_plan_schedule": (st, [_vp, _i32p, _i32p]),
@@ -443,17 +445,29 @@ class Plan:
     """A fused execution plan (host object built by the library).
 
     image=False builds it for scoring only (schedule, statistics and pass
-    features without block matrices or device image); such a plan cannot run."""
+    features without block matrices or device image); such a plan cannot run.
+    k_of_pass: tile passes whose block width is chosen per pass
+    (qvm_plan_tile_per_pass; k_max is then ignored)."""
 
     def __init__(self, gates, n: int, dtype: str = "c64", k_max: int = 5, tile_qubits: int = 0,
-                 partition=None, image: bool = True):
+                 partition=None, image: bool = True, k_of_pass=None):
         _declare_plan(lib())
         self.gates = gates if isinstance(gates, GateArray) else GateArray(gates)
         self.n = int(n)
         self.dtype = "c64" if _dt(dtype) == QVM_C64 else "c128"
         self.k_max, self.tile_qubits, self.image = int(k_max), int(tile_qubits), bool(image)
         h = _vp()
-        if partition is None:
+        self.k_of_pass = None if k_of_pass is None else [int(k) for k in k_of_pass]
+        if k_of_pass is not None:
+            if partition is not None:
+                raise ValueError("k_of_pass and partition are exclusive")
+            ks = np.ascontiguousarray(k_of_pass, dtype=np.int32)
+            self.k_max = int(ks.max()) if ks.size else 0
+            flags = 0 if image else QVM_PLAN_NO_IMAGE
+            check(lib().qvm_plan_tile_per_pass(self.gates.ptr(), self.gates.n, self.n, int(tile_qubits),
+                                               ks.ctypes.data_as(_i32p), int(ks.size), _dt(dtype), flags,
+                                               ctypes.byref(h)))
+        elif partition is None:
             flags = 0 if image else QVM_PLAN_NO_IMAGE
             check(lib().qvm_plan_greedy_ex(self.gates.ptr(), self.gates.n, self.n, int(k_max),
                                            int(tile_qubits), _dt(dtype), flags, ctypes.byref(h)))

@@ -40,48 +40,57 @@ def test_collect_train_choose(tmp_path):
     tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
                          + 5 * st["diag_ops"]) * U32
     assert np.max(np.abs(sv.amplitudes() - want)) <= tau
-    recs, checks = lp.evaluate(planner, 20_000, 4, all_cands=2, check_amplitudes=2,
-                               n_range=(13, 15), g_range=(60, 100))
-    summ = lp.summarize(recs, checks)
-    assert summ["circuits"] == 4 and summ["max_abs_err_vs_c128"] < 1e-5
+    recs = lp.evaluate(planner, 20_000, 4, n_range=(13, 15), g_range=(60, 100), log=False)
+    summ = lp.summarize(recs)
+    assert summ["circuits"] == 4 and summ["amplitude_checks"] == 4
+    assert summ["max_abs_err_vs_c128"] < 1e-5
 
 
-def test_trained_model_gains_over_greedy():
-    """The shipped model against the greedy planner's classic setting (one
-    5-qubit block per pass) on held-out circuits from the training
-    distribution (26-28 qubits, 100-500 gates): measured total time of the
-    learned choices must not exceed the greedy total, and the learned plan's
-    amplitudes must agree with the plain complex128 path."""
+def plan_tau(plan):
+    st = plan.stats()
+    return 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
+                          + 5 * st["diag_ops"]) * U32
+
+
+def test_trained_model_against_the_fallback():
+    """The shipped model on held-out circuits of the planner workload (26-28
+    qubits, 100-500 gates) against the greedy planner without it (its
+    fallback setting, 4-qubit blocks in 13-qubit tiles): the measured total
+    of the learned choices must not exceed the fallback's by more than 2%
+    (the gain is printed), and the learned plan's whole state must agree
+    with the plain complex128 path within 1e-5."""
     from paper_2212_14201_amd import qvm
     planner = lp.load_default()
     if planner is None:
         pytest.skip("no trained model shipped")
-    pool = lp.StatePool()
-    learned = greedy = 0.0
-    for s in range(100_000, 100_006):
-        n, gates = random_planner_circuit(s, n_range=(26, 28), g_range=(100, 500))
-        ga = qvm.GateArray(gates)
-        cand, plan, _ = planner.choose(ga, n, "c64")
-        sv = pool.get(n, "c64")
-        lp.time_plan(sv, plan)                        # warm-up
-        lms = lp.time_plan(sv, plan)[0]
-        gms = lp.time_plan(sv, lp.build_plan(ga, n, "c64", lp.GREEDY))[0]
-        print(f"seed {s} n={n} gates={len(gates)} choice={cand}: learned {lms:.2f} ms, greedy {gms:.2f} ms")
-        learned += lms
-        greedy += gms
-    print(f"gain over greedy: {greedy / learned:.2f}x")
-    assert learned <= greedy
-    # the last circuit's learned plan against the plain complex128 path
-    sv.init_basis(0)
-    plan.run(sv)
-    del pool
-    plain = qvm.StateVector(n, "c128", init=0)
-    plain.run(ga)
-    idx = np.random.default_rng(s).integers(0, 1 << n, 4096, dtype=np.uint64)
-    st = plan.stats()
-    tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
-                         + 5 * st["diag_ops"]) * U32
-    assert np.max(np.abs(sv.gather(idx) - plain.gather(idx))) <= tau
+    recs = lp.evaluate(planner, 100_000, 6, n_range=(26, 28), g_range=(100, 500), log=False)
+    for r in recs:
+        print(f"seed {r['seed']} n={r['n']} gates={r['gates']} choice={r['choice']}: learned "
+              f"{r['learned_ms']:.2f} ms, fallback {r['all_ms'][lp.cand_name(lp.FALLBACK)]:.2f} ms, "
+              f"error vs complex128 {r['max_abs_err_vs_c128']:.1e}")
+    summ = lp.summarize(recs)
+    print("summary:", summ)
+    fb = summ["vs_fallback"]
+    assert summ["learned_total_ms"] <= 1.02 * fb["total_ms"]
+    assert summ["within_1e-5"] == len(recs)
+
+
+def test_adaptive_plan_on_gpu():
+    """A plan whose passes each take their own block width (3..5) runs on
+    the GPU and reproduces the oracle in both dtypes."""
+    from paper_2212_14201_amd import qvm
+    n, gates = random_planner_circuit(100_321, n_range=(15, 15), g_range=(200, 200))
+    want = oracle.simulate(n, gates, init=5)
+    for dtype, tile in (("c64", 12), ("c128", 11)):
+        npass = qvm.Plan(gates, n, dtype, k_max=3, tile_qubits=tile, image=False).stats()["passes"]
+        ks = np.random.default_rng(7).integers(3, 6, npass)
+        plan = qvm.Plan(gates, n, dtype, tile_qubits=tile, k_of_pass=ks)
+        sv = qvm.StateVector(n, dtype, init=5)
+        plan.run(sv)
+        err = float(np.max(np.abs(sv.amplitudes() - want)))
+        tol = plan_tau(plan) if dtype == "c64" else 1e-12
+        print(f"{dtype}: widths {ks.tolist()}, error {err:.1e} (bound {tol:.1e})")
+        assert err <= tol
 
 
 def test_plan_front_end_with_the_learned_planner():
@@ -96,7 +105,4 @@ def test_plan_front_end_with_the_learned_planner():
     sv = qvm.StateVector(n, "c64", init=3)
     plan.run(sv)
     want = oracle.simulate(n, gates, init=3)
-    st = plan.stats()
-    tau = 10 * math.sqrt(sum((1 << plan.block(b)["k"]) + 4 for b in range(st["blocks"]))
-                         + 5 * st["diag_ops"]) * U32
-    assert np.max(np.abs(sv.amplitudes() - want)) <= tau
+    assert np.max(np.abs(sv.amplitudes() - want)) <= plan_tau(plan)

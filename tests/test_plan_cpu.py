@@ -396,3 +396,54 @@ def test_python_layer_names():
         qvm.plan(list(c), planner="greedy")
     adj = pytest.importorskip("paper_2212_14201_amd.adjoint")
     assert qvm.AdjointExpectation is adj._function()
+
+
+def pass_gate_sets(plan, ngates):
+    """The gates of each pass: execution positions are consecutive within a
+    pass, and each pass's gate count is its pass feature 10."""
+    from paper_2212_14201_amd import learned_planner
+    counts = learned_planner.plan_features(plan)[:, 10].astype(int)
+    pos, unit = plan.schedule()
+    order = [i for i in np.argsort(pos, kind="stable") if pos[i] >= 0]
+    out, o = [], 0
+    for c in counts:
+        out.append(frozenset(order[o:o + c]))
+        o += c
+    assert o == len(order)
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_per_pass_block_widths(seed):
+    """Tile passes take the same gates whatever the block width, so a plan
+    with a width per pass has pass i of every fixed-width plan; it is valid,
+    its blocks respect each pass's width, and with one width throughout it
+    is the fixed-width plan."""
+    n, gates = random_planner_circuit(7000 + seed, n_range=(14, 16), g_range=(150, 250))
+    ga = qvm.GateArray(gates)
+    fixed = {k: qvm.Plan(ga, n, "c64", k_max=k, tile_qubits=11) for k in (3, 4, 5)}
+    sets = {k: pass_gate_sets(p, len(gates)) for k, p in fixed.items()}
+    assert sets[3] == sets[4] == sets[5]
+    npass = fixed[3].stats()["passes"]
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(3, 6, npass).astype(np.int32)
+    plan = qvm.Plan(ga, n, "c64", tile_qubits=11, k_of_pass=ks)
+    assert pass_gate_sets(plan, len(gates)) == sets[3]
+    units = units_in_order(plan, len(gates))
+    wg = on_wires(gates)
+    kept = sorted(wg)
+    remap = {g: j for j, g in enumerate(kept)}
+    ok, why = oracle.validate_plan([wg[i] for i in kept], [[remap[i] for i in u] for u in units], n)
+    assert ok, why
+    for b in range(plan.stats()["blocks"]):
+        blk = plan.block(b)
+        assert blk["k_true"] <= ks[blk["pass"]]
+        want = oracle.block_matrix([wg[i] for i in blk["gates"]], blk["qubits"])
+        assert np.max(np.abs(blk["matrix"] - want)) < 1e-13
+    for k in (3, 4, 5):
+        same = qvm.Plan(ga, n, "c64", tile_qubits=11, k_of_pass=[k])
+        assert same.stats() == fixed[k].stats()
+    with pytest.raises(qvm.QvmError):
+        qvm.Plan(ga, n, "c64", tile_qubits=0, k_of_pass=[3])
+    with pytest.raises(qvm.QvmError):
+        qvm.Plan(ga, n, "c128", tile_qubits=12, k_of_pass=[3, 6])
