@@ -404,6 +404,34 @@ qvm_status qvm_adjoint_expect_grad(int n_qubits, qvm_dtype dt, int batch,
                                    void* work_dev, size_t work_bytes, void* hip_stream,
                                    double* f_out, double* grad_out);
 
+/* Size of the library's static adjoint workspace (64 MiB per device). */
+#define QVM_ADJ_SCRATCH_BYTES (64u << 20)
+
+/* qvm_adjoint_expect_grad without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the workspace is a static array
+ * of QVM_ADJ_SCRATCH_BYTES in the library, one per device, allocated when
+ * the library's code object is loaded on that device and held until the
+ * process ends.  This call allocates no device memory.  The caller still
+ * owns psi_dev and lam_dev (batch x 2^n amplitudes each) and the outputs;
+ * results are identical to qvm_adjoint_expect_grad's.  A problem whose
+ * workspace (matrices 2 x n_gates x batch x 64 bytes, plus reduction
+ * partials (trainable gates + 1) x batch x 520 bytes, plus the op table)
+ * exceeds QVM_ADJ_SCRATCH_BYTES returns QVM_ENOMEM before anything is
+ * enqueued; 20 qubits, 944 gates of which 640 trainable, batch 64 needs
+ * about 29 MB.  Every call on one device shares that device's array:
+ * calls that overlap on one device (other host threads, or other streams
+ * before this one's synchronisation) race and give wrong results.  The
+ * call is synchronous on hip_stream, so calls made one after another are
+ * safe; no contents carry over between calls. */
+qvm_status qvm_adjoint_expect_grad_static(int n_qubits, qvm_dtype dt, int batch,
+                                          const qvm_gate* gates, size_t n_gates,
+                                          const int32_t* param_index, int n_params,
+                                          const double* params_host, size_t n_terms,
+                                          const uint64_t* x_mask, const uint64_t* z_mask,
+                                          const double* coeff, void* psi_dev, void* lam_dev,
+                                          void* hip_stream, double* f_out, double* grad_out);
+
 /* ------------------------------------------------------------ cost model */
 
 /* A three-layer perceptron (d features -> H -> H -> 1, ReLU) that predicts

@@ -18,14 +18,24 @@ def _declare():
                                           ctypes.c_size_t, _u64p, _u64p, _dp, _vp, _vp, _vp,
                                           ctypes.c_size_t, _vp, _dp, _dp]
     L.qvm_adjoint_expect_grad.restype = ctypes.c_int
+    L.qvm_adjoint_expect_grad_static.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _gp,
+                                                 ctypes.c_size_t, _i32p, ctypes.c_int, _dp,
+                                                 ctypes.c_size_t, _u64p, _u64p, _dp, _vp, _vp, _vp,
+                                                 _dp, _dp]
+    L.qvm_adjoint_expect_grad_static.restype = ctypes.c_int
     return L
 
 
 class AdjointProblem:
     """A parameterised circuit and a Pauli-sum observable, with device
-    buffers for a batch of states (psi, lambda) allocated once."""
+    buffers for a batch of states (psi, lambda) allocated once.
 
-    def __init__(self, n, gates, n_params, xs, zs, cs, batch, dtype="c64", device="cuda"):
+    static_workspace: run through ``qvm_adjoint_expect_grad_static``, whose
+    workspace is the library's static per-device array (no workspace
+    tensor is allocated here)."""
+
+    def __init__(self, n, gates, n_params, xs, zs, cs, batch, dtype="c64", device="cuda",
+                 static_workspace=False):
         import torch
         self.n, self.batch, self.n_params = int(n), int(batch), int(n_params)
         self.dtype = dtype
@@ -38,9 +48,12 @@ class AdjointProblem:
         self.device = torch.device(device)
         self.psi = torch.empty(self.batch * (2 << self.n), dtype=real, device=self.device)
         self.lam = torch.empty_like(self.psi)
-        L = _declare()
-        self.work = torch.empty(int(L.qvm_adjoint_workspace_bytes(self.n, self.batch, self.gates.n)),
-                                dtype=torch.uint8, device=self.device)
+        self.static_workspace = bool(static_workspace)
+        self.work = None
+        if not self.static_workspace:
+            L = _declare()
+            self.work = torch.empty(int(L.qvm_adjoint_workspace_bytes(self.n, self.batch, self.gates.n)),
+                                    dtype=torch.uint8, device=self.device)
 
     def run(self, params, want_grad=True):
         """params: array [batch, n_params].  Returns (f[batch], grad[batch, n_params] or None)."""
@@ -49,12 +62,17 @@ class AdjointProblem:
         f = np.zeros(self.batch, dtype=np.float64)
         g = np.zeros((self.batch, self.n_params), dtype=np.float64) if want_grad else None
         stream = torch.cuda.current_stream(self.device).cuda_stream
-        check(_declare().qvm_adjoint_expect_grad(
-            self.n, _dt(self.dtype), self.batch, self.gates.ptr(), self.gates.n,
-            self.pidx.ctypes.data_as(_i32p), self.n_params, p.ctypes.data_as(_dp), self.xs.size,
-            self.xs.ctypes.data_as(_u64p), self.zs.ctypes.data_as(_u64p), self.cs.ctypes.data_as(_dp),
-            self.psi.data_ptr(), self.lam.data_ptr(), self.work.data_ptr(), self.work.numel(), stream,
-            f.ctypes.data_as(_dp), g.ctypes.data_as(_dp) if want_grad else None))
+        common = (self.n, _dt(self.dtype), self.batch, self.gates.ptr(), self.gates.n,
+                  self.pidx.ctypes.data_as(_i32p), self.n_params, p.ctypes.data_as(_dp), self.xs.size,
+                  self.xs.ctypes.data_as(_u64p), self.zs.ctypes.data_as(_u64p), self.cs.ctypes.data_as(_dp),
+                  self.psi.data_ptr(), self.lam.data_ptr())
+        outs = (f.ctypes.data_as(_dp), g.ctypes.data_as(_dp) if want_grad else None)
+        L = _declare()
+        with torch.cuda.device(self.device):
+            if self.static_workspace:
+                check(L.qvm_adjoint_expect_grad_static(*common, stream, *outs))
+            else:
+                check(L.qvm_adjoint_expect_grad(*common, self.work.data_ptr(), self.work.numel(), stream, *outs))
         return f, g
 
 

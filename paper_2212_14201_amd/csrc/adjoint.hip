@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -571,6 +572,48 @@ static qvm_status adj_prepare(int n, int batch, const qvm_gate* gates, size_t n_
     return QVM_OK;
 }
 
+// Trainable gates: the gradient rows the sweep fills (plus row 0, f).
+size_t adj_trainable(const std::vector<AdjGate>& G) {
+    size_t t = 0;
+    for (const AdjGate& g : G) t += g.pidx >= 0;
+    return t;
+}
+
+qvm_status adj_dispatch(int n, qvm_dtype dt, int batch, const std::vector<AdjGate>& G, int n_params,
+                        const double* params_host, const std::vector<PauliTerms>& terms, void* psi_dev,
+                        void* lam_dev, char* work, const AdjLayout& L, void* hip_stream, double* f_out,
+                        double* grad_out);
+
+// Workspace of qvm_adjoint_expect_grad_static: one array per device, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in for the symbol): its
+// device address is looked up once per device, with that device current,
+// and kept below.  Every entry a call reads is written earlier in the same
+// call (matrices and op table copied in, each reduction partial stored by
+// its block), so nothing needs clearing between calls.
+static __device__ __align__(256) char scratch[QVM_ADJ_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static char* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+qvm_status adj_scratch(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(QVM_EDEVICE, std::string("adjoint: hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return adj_fail(QVM_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(QVM_EDEVICE, std::string("adjoint: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (char*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return QVM_OK;
+}
+
 }  // namespace qvm
 
 using namespace qvm;
@@ -597,16 +640,52 @@ qvm_status qvm_adjoint_expect_grad(int n, qvm_dtype dt, int batch, const qvm_gat
     qvm_status st = adj_prepare(n, batch, gates, n_gates, param_index, n_params, n_terms, x_mask,
                                 z_mask, coeff, G, terms);
     if (st) return st;
-    AdjLayout L = adj_layout(batch, G.size(), G.size());
+    const AdjLayout L = adj_layout(batch, G.size(), adj_trainable(G));
     if (work_bytes < L.total) return adj_fail(QVM_ENOMEM, "workspace too small");
-    const bool want = grad_out != nullptr;
-    if (dt == QVM_C64)
-        return adjoint_t<float>(n, batch, G, n_params, params_host, terms.data(), (int)terms.size(),
-                                psi_dev, lam_dev, (char*)work_dev, L, (hipStream_t)hip_stream, want,
-                                f_out, grad_out);
-    return adjoint_t<double>(n, batch, G, n_params, params_host, terms.data(), (int)terms.size(),
-                             psi_dev, lam_dev, (char*)work_dev, L, (hipStream_t)hip_stream, want,
-                             f_out, grad_out);
+    return adj_dispatch(n, dt, batch, G, n_params, params_host, terms, psi_dev, lam_dev, (char*)work_dev, L,
+                        hip_stream, f_out, grad_out);
+}
+
+qvm_status qvm_adjoint_expect_grad_static(int n, qvm_dtype dt, int batch, const qvm_gate* gates,
+                                          size_t n_gates, const int32_t* param_index, int n_params,
+                                          const double* params_host, size_t n_terms,
+                                          const uint64_t* x_mask, const uint64_t* z_mask,
+                                          const double* coeff, void* psi_dev, void* lam_dev,
+                                          void* hip_stream, double* f_out, double* grad_out) {
+    if (dt != QVM_C64 && dt != QVM_C128) return adj_fail(QVM_EARG, "unknown dtype");
+    if (!psi_dev || !lam_dev || !f_out) return adj_fail(QVM_EARG, "NULL buffer");
+    if (n_params > 0 && !params_host) return adj_fail(QVM_EARG, "NULL parameters");
+    if (psi_dev == lam_dev) return adj_fail(QVM_EARG, "psi and lambda must not alias");
+    std::vector<AdjGate> G;
+    std::vector<PauliTerms> terms;
+    qvm_status st = adj_prepare(n, batch, gates, n_gates, param_index, n_params, n_terms, x_mask,
+                                z_mask, coeff, G, terms);
+    if (st) return st;
+    const AdjLayout L = adj_layout(batch, G.size(), adj_trainable(G));
+    if (L.total > QVM_ADJ_SCRATCH_BYTES)
+        return adj_fail(QVM_ENOMEM, "needs " + std::to_string(L.total) + " bytes of workspace, the static "
+                        "scratch holds " + std::to_string((size_t)QVM_ADJ_SCRATCH_BYTES));
+    char* work = nullptr;
+    st = adj_scratch(&work);
+    if (st) return st;
+    return adj_dispatch(n, dt, batch, G, n_params, params_host, terms, psi_dev, lam_dev, work, L, hip_stream,
+                        f_out, grad_out);
 }
 
 }  // extern "C"
+
+namespace qvm {
+
+qvm_status adj_dispatch(int n, qvm_dtype dt, int batch, const std::vector<AdjGate>& G, int n_params,
+                        const double* params_host, const std::vector<PauliTerms>& terms, void* psi_dev,
+                        void* lam_dev, char* work, const AdjLayout& L, void* hip_stream, double* f_out,
+                        double* grad_out) {
+    const bool want = grad_out != nullptr;
+    if (dt == QVM_C64)
+        return adjoint_t<float>(n, batch, G, n_params, params_host, terms.data(), (int)terms.size(),
+                                psi_dev, lam_dev, work, L, (hipStream_t)hip_stream, want, f_out, grad_out);
+    return adjoint_t<double>(n, batch, G, n_params, params_host, terms.data(), (int)terms.size(),
+                             psi_dev, lam_dev, work, L, (hipStream_t)hip_stream, want, f_out, grad_out);
+}
+
+}  // namespace qvm
