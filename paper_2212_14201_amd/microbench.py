@@ -9,6 +9,7 @@ counters for a plain device copy of known size (the scale factor).
     python -m paper_2212_14201_amd.microbench --kernel copy --n 30 --dtype c128
     python -m paper_2212_14201_amd.microbench --kernel stream --n 30 --launches 5
     python -m paper_2212_14201_amd.microbench --kernel blocks --k 4 --blocks 32 --n 30 --launches 2
+    python -m paper_2212_14201_amd.microbench --kernel phase --qubits 0 1 --n 30 --dtype c128
 """
 import argparse
 import os
@@ -19,7 +20,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=["dense1", "tile", "copy", "stream", "blocks"], required=True)
+    ap.add_argument("--kernel", choices=["dense1", "phase", "tile", "copy", "stream", "blocks"], required=True)
+    ap.add_argument("--qubits", type=int, nargs=2, default=(0, 1), help="phase: the CZ's control and target")
     ap.add_argument("--k", type=int, default=4, help="blocks: block width in qubits")
     ap.add_argument("--blocks", type=int, default=32, help="blocks: fused blocks in the one tile pass")
     ap.add_argument("--n", type=int, default=30)
@@ -98,8 +100,11 @@ def main():
         print(f"copy of {src.numel() * src.element_size()} bytes x {a.launches}", flush=True)
         return
     sv = qvm.StateVector(a.n, a.dtype, init=0)
-    if a.kernel == "dense1":
-        g = Gate("u3", (a.n // 3,), (), (0.3, 0.2, 0.1))
+    if a.kernel in ("dense1", "phase"):
+        # dense1: a U3 on qubit n/3; phase: one CZ (a phase on the quarter of
+        # the amplitudes with both bits set)
+        g = (Gate("u3", (a.n // 3,), (), (0.3, 0.2, 0.1)) if a.kernel == "dense1"
+             else Gate("z", (a.qubits[1],), (a.qubits[0],)))
         for _ in range(a.launches):
             sv.apply(g)
     else:
