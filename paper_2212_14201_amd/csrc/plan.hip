@@ -315,7 +315,7 @@ struct Builder {
     size_t put(const void* p, size_t bytes) {
         size_t off = (blob.size() + 255) & ~size_t(255);
         blob.resize(off + bytes);
-        memcpy(blob.data() + off, p, bytes);
+        if (bytes) memcpy(blob.data() + off, p, bytes);
         return off;
     }
 };
@@ -394,52 +394,88 @@ int run_bitmap(int L, int8_t* bitmap) {
     return L > kLogTileThreads ? L - kLogTileThreads : 0;
 }
 
-// The element layout of a complex64 block epilogue in a 13-qubit tile
-// (3- or 4-qubit block, one column iteration per wave; tile.hip): lane
-// l = 0..63, wave w, column tile ct < CT (8 for k = 3, 4 for k = 4) and
-// row block rb < K / 16 hold column (CT w + ct) 16 + (l & 15) of the tile
-// bits outside the block (in ascending order) and complex row
-// 8 rb + 2 (l >> 4) + hh of the block, hh = 0, 1.  Thread code:
-// (l & 15) | (l >> 4) << 4 | w << 6; element code: hh | ct << 1 | rb << (1 + log2 CT).
-bool epilogue_bitmap(const int32_t* lb, int k, int L, qvm_dtype dt, int8_t* bitmap) {
-    if (dt != QVM_C64 || L != 13 || (k != 3 && k != 4)) return false;
-    const int lct = k == 3 ? 3 : 2;
+// Column roles of a block op (layout in tile.hpp): the tile bits outside
+// the block, in ascending order, give the lane's four column bits and then
+// the bits of the column-tile index ti; with wave bits W (three tile bits
+// outside the block), W takes the ti bits above the CT bits (the wave's)
+// and the other bits keep ascending order around it.  W = 0 is the default
+// layout (every role in ascending order).
+struct ColMap {
+    int nlane = 0;
+    int lane[4] = {0, 0, 0, 0};
+    std::vector<int> tib;          // tile bit of ti bit j
+};
+
+ColMap col_map(const int32_t* lb, int k, int L, qvm_dtype dt, uint32_t W) {
     uint32_t bmask = 0;
     for (int r = 0; r < k; ++r) bmask |= 1u << lb[r];
-    for (int b = 0, m = 0; b < L; ++b) {
-        if ((bmask >> b) & 1) continue;
-        bitmap[b] = (int8_t)(m < 4 ? m : m < 4 + lct ? 32 + 1 + (m - 4) : 6 + (m - 4 - lct));
-        ++m;
+    std::vector<int> rest;
+    for (int b = 0; b < L; ++b)
+        if (!((bmask >> b) & 1) && !((W >> b) & 1)) rest.push_back(b);
+    ColMap m;
+    m.nlane = std::min(4, (int)rest.size());
+    for (int i = 0; i < m.nlane; ++i) m.lane[i] = rest[i];
+    rest.erase(rest.begin(), rest.begin() + m.nlane);
+    if (!W) {
+        m.tib = rest;
+        return m;
     }
+    const int ct = block_ct(k, L, dt == QVM_C128);
+    int lct = 0;
+    while ((1 << lct) < ct) ++lct;
+    m.tib.assign(rest.begin(), rest.begin() + lct);
+    for (int b = 0; b < L; ++b)
+        if ((W >> b) & 1) m.tib.push_back(b);
+    m.tib.insert(m.tib.end(), rest.begin() + lct, rest.end());
+    return m;
+}
+
+// Blocks whose waves may keep their elements across blocks: up to 4 qubits
+// (register fragments) and at least one full iteration of column tiles per
+// wave (ntile >= 8 CT), so that ti has three wave bits.
+bool wave_bits_ok(int k, int L, qvm_dtype dt) {
+    if (k > 4 || L - k < 4) return false;
+    const int ntile = 1 << (L - k - 4);
+    return ntile >= 8 * block_ct(k, L, dt == QVM_C128);
+}
+
+// A diagonal run can ride in the epilogue of a complex64 3- or 4-qubit block
+// in a 13-qubit tile (one column iteration per wave; tile.hip).
+bool epilogue_ok(int k, int L, qvm_dtype dt) { return dt == QVM_C64 && L == 13 && (k == 3 || k == 4); }
+
+// The element layout of such an epilogue: lane l = 0..63, wave w, column
+// tile ct < CT (8 for k = 3, 4 for k = 4) and row block rb < K / 16 hold
+// column tile CT w + ct, the lane's column l & 15, and complex row
+// 8 rb + 2 (l >> 4) + hh of the block, hh = 0, 1.  Thread code:
+// (l & 15) | (l >> 4) << 4 | w << 6; element code: hh | ct << 1 | rb << (1 + log2 CT).
+// bitmap[b] = thread-code bit of tile bit b, or 32 + its element-code bit.
+void epilogue_bitmap(const int32_t* lb, int k, const ColMap& cm, int8_t* bitmap) {
+    const int lct = k == 3 ? 3 : 2;
+    for (int i = 0; i < cm.nlane; ++i) bitmap[cm.lane[i]] = (int8_t)i;
+    for (int j = 0; j < (int)cm.tib.size(); ++j)
+        bitmap[cm.tib[j]] = (int8_t)(j < lct ? 32 + 1 + j : 6 + (j - lct));
     for (int r = 0; r < k; ++r)
         bitmap[lb[r]] = (int8_t)(r == 0 ? 32 : r <= 2 ? 4 + (r - 1) : 32 + 1 + lct);
-    return true;
 }
 
 // Address table of a block op (layout in tile.hpp): the wave-uniform parts
 // of its LDS slots, computed once here instead of per access in the kernel.
-std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt) {
+std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt, const ColMap& cm) {
     auto rows = [&](int j) {                     // block row index -> tile bits
         uint32_t e = 0;
         for (int q = 0; q < k; ++q)
             if ((j >> q) & 1) e |= 1u << lb[q];
         return e;
     };
-    uint32_t bmask = 0;
-    for (int q = 0; q < k; ++q) bmask |= 1u << lb[q];
-    auto deposit = [&](uint32_t w) {             // w over the tile bits outside the block
-        uint32_t e = 0;
-        for (int i = 0, b = 0; i < L; ++i) {
-            if ((bmask >> i) & 1) continue;
-            if ((w >> b) & 1) e |= 1u << i;
-            ++b;
-        }
-        return e;
-    };
     const BlockTabLayout lay(L, k);
     const uint32_t es = dt == QVM_C64 ? 8u : 16u;     // bytes per amplitude
     std::vector<uint32_t> t((size_t)lay.words(), 0u);
-    for (int ti = 0; ti < lay.ntile; ++ti) t[lay.col() + ti] = es * tile_swizzle(deposit(16u * ti));
+    for (int ti = 0; ti < lay.ntile; ++ti) {
+        uint32_t e = 0;
+        for (int j = 0; j < (int)cm.tib.size(); ++j)
+            if ((ti >> j) & 1) e |= 1u << cm.tib[j];
+        t[lay.col() + ti] = es * tile_swizzle(e);
+    }
     for (int i = 0; i < lay.nb; ++i) t[lay.brow() + i] = es * tile_swizzle(rows(4 * i));
     for (int rb = 0; rb < lay.ne / 4; ++rb)
         for (int r = 0; r < 4; ++r) {
@@ -449,6 +485,7 @@ std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt)
             const int j = dt == QVM_C64 ? (r < 2 ? 8 * rb + r : -1) : 8 * rb + 2 * r;
             t[lay.erow() + 4 * rb + r] = j < 0 ? 0u : es * tile_swizzle(rows(j));
         }
+    for (int i = 0; i < cm.nlane; ++i) t[lay.lane() + i] = es * tile_swizzle(1u << cm.lane[i]);
     return t;
 }
 
@@ -697,6 +734,9 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         const int pi = (int)P->passes.size();
         std::vector<TOp> ops;
         std::vector<DSub> run;
+        // runs that ride in a block's epilogue: encoded once the block's
+        // column layout is fixed (after the wave bits are chosen)
+        std::vector<std::pair<size_t, std::vector<DSub>>> epi_runs;
         // Diagonal gates commute with each other and with blocks on other
         // wires, so they are held back until a block touches one of their
         // wires (or the pass ends) and then emitted as one run: fewer, longer
@@ -724,22 +764,35 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
             int8_t bitmap[32];
             const bool fuse_prev = !ops.empty() && ops.back().type == TOP_BLOCK &&
-                                   !(ops.back().flags & BLK_RUN) &&
-                                   epilogue_bitmap(ops.back().lb, ops.back().k, L, dt, bitmap);
-            if (fuse_prev || (int)run.size() >= at_least) {
-                // the angle path; right after a 3- or 4-qubit block the run
-                // is applied in that block's epilogue (no pass of its own)
-                const int nhb = fuse_prev ? 4 : run_bitmap(L, bitmap);
+                                   !(ops.back().flags & BLK_RUN) && epilogue_ok(ops.back().k, L, dt);
+            if (fuse_prev) {
+                // applied in the block's epilogue (no pass of its own); the
+                // default layout tells whether the run's phases cancel
+                epilogue_bitmap(ops.back().lb, ops.back().k, col_map(ops.back().lb, ops.back().k, L, dt, 0), bitmap);
+                std::vector<DTerm> terms;
+                std::vector<uint32_t> off;
+                angle_terms(run, L, dt, bitmap, 4, terms, off);
+                if (terms.empty()) {
+                    run.clear();
+                    return;
+                }
+                op.k = (int32_t)terms.size();
+                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0) | DRUN_EPILOGUE;
+                ops.back().flags |= BLK_RUN;
+                epi_runs.emplace_back(ops.size(), std::move(run));
+                run.clear();
+            } else if ((int)run.size() >= at_least) {
+                // the angle path
+                const int nhb = run_bitmap(L, bitmap);
                 std::vector<DTerm> terms;
                 std::vector<uint32_t> off;
                 angle_terms(run, L, dt, bitmap, nhb, terms, off);
                 run.clear();
                 if (terms.empty()) return;          // the run's phases cancel
                 op.k = (int32_t)terms.size();
-                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0) | (fuse_prev ? DRUN_EPILOGUE : 0);
+                op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0);
                 op.data = B.put(terms.data(), terms.size() * sizeof(DTerm));
                 op.tab = B.put(off.data(), off.size() * sizeof(uint32_t));
-                if (fuse_prev) ops.back().flags |= BLK_RUN;
             } else {
                 op.k = (int32_t)run.size();
                 op.data = B.put(run.data(), run.size() * sizeof(DSub));
@@ -767,8 +820,6 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 for (int r = 0; r < k; ++r) op.lb[r] = local_of_wire[bq[r]];
                 if (image) {
                     M = block_matrix(G, u.gates, bq);
-                    const std::vector<uint32_t> tab = block_table(op.lb, k, L, dt);
-                    op.tab = B.put(tab.data(), tab.size() * sizeof(uint32_t));
                     if (dt == QVM_C64) {
                         auto f = fragments<float>(M, k);
                         op.data = B.put(f.data(), f.size() * sizeof(float));
@@ -830,6 +881,83 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             ops.push_back(op);
         }
         flush();
+        // ---- wave bits.  In a pass whose blocks are all of 3 or 4 qubits
+        // (register fragments), consecutive blocks that leave three tile bits
+        // W untouched form an epoch: every block of it puts W on its wave
+        // bits, so each wave owns the elements with one value of W throughout
+        // and the blocks after the first need no workgroup barrier
+        // (BLK_NOSYNC).  Standalone diagonal runs (their own layout) end an
+        // epoch; epilogue runs ride with their block.
+        std::vector<uint32_t> wsel(ops.size(), 0u);
+        {
+            int kmax_pass = 0;
+            for (const TOp& o : ops)
+                if (o.type == TOP_BLOCK) kmax_pass = std::max(kmax_pass, (int)o.k);
+            if (kmax_pass <= 4) {
+                const uint32_t tile_bits = (1u << L) - 1;
+                std::vector<size_t> members;
+                uint32_t allowed = 0;
+                auto close = [&]() {
+                    if (members.size() >= 2) {
+                        uint32_t W = 0;
+                        for (int b = L - 1, got = 0; b >= 0 && got < 3; --b)
+                            if ((allowed >> b) & 1) {
+                                W |= 1u << b;
+                                ++got;
+                            }
+                        for (size_t i = 0; i < members.size(); ++i) {
+                            wsel[members[i]] = W;
+                            if (i) ops[members[i]].flags |= BLK_NOSYNC;
+                        }
+                    }
+                    members.clear();
+                    allowed = 0;
+                };
+                for (size_t oi = 0; oi < ops.size(); ++oi) {
+                    const TOp& o = ops[oi];
+                    if (o.type != TOP_BLOCK) {
+                        if (!(o.flags & DRUN_EPILOGUE)) close();
+                        continue;
+                    }
+                    if (!wave_bits_ok(o.k, L, dt)) {
+                        close();
+                        continue;
+                    }
+                    uint32_t bm = 0;
+                    for (int r = 0; r < o.k; ++r) bm |= 1u << o.lb[r];
+                    const uint32_t ok = tile_bits & ~bm;
+                    if (!members.empty() && __builtin_popcount(allowed & ok) >= 3) {
+                        allowed &= ok;
+                        members.push_back(oi);
+                    } else {
+                        close();
+                        members.push_back(oi);
+                        allowed = ok;
+                    }
+                }
+                close();
+            }
+        }
+        // ---- block address tables and epilogue runs over the final layouts
+        for (auto& er : epi_runs) {
+            TOp& o = ops[er.first];
+            const TOp& blk = ops[er.first - 1];
+            int8_t bitmap[32];
+            epilogue_bitmap(blk.lb, blk.k, col_map(blk.lb, blk.k, L, dt, wsel[er.first - 1]), bitmap);
+            std::vector<DTerm> terms;
+            std::vector<uint32_t> off;
+            angle_terms(er.second, L, dt, bitmap, 4, terms, off);
+            o.k = (int32_t)terms.size();
+            o.data = B.put(terms.data(), terms.size() * sizeof(DTerm));
+            o.tab = B.put(off.data(), off.size() * sizeof(uint32_t));
+        }
+        if (image)
+            for (size_t oi = 0; oi < ops.size(); ++oi) {
+                TOp& o = ops[oi];
+                if (o.type != TOP_BLOCK) continue;
+                const std::vector<uint32_t> tab = block_table(o.lb, o.k, L, dt, col_map(o.lb, o.k, L, dt, wsel[oi]));
+                o.tab = B.put(tab.data(), tab.size() * sizeof(uint32_t));
+            }
         PassDesc pd{};
         pd.L = L;
         pd.c = c;

@@ -197,9 +197,15 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // as l % 16 and block bits 1, 2 as l / 16; the wave holds the top column
 // bits) and element code hh | ct << 1 | rb << (1 + log2 CT) (block bit 0,
 // the column tile, block bit 3).
-template <typename R, int K, int LT, bool RUN = false>
-__device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const TOp& op,
-                                           const char* __restrict__ blob, int L_,
+//
+// With GA (blocks of up to 4 qubits in passes without wider blocks) the A
+// fragments come from the caller's registers (fetched from the plan one
+// block ahead) instead of the LDS fragment area.
+constexpr int NFA = 16;            // fragment registers per lane for GA blocks (k <= 4, complex64 or 128)
+
+template <typename R, int K, int LT, bool RUN = false, bool GA = false>
+__device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NFA],
+                                           const TOp& op, const char* __restrict__ blob, int L_,
                                            const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
     static_assert(!RUN || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
@@ -215,17 +221,12 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     // (at most the wave's share of the tile's column tiles, so that narrower
     // tiles keep every wave busy)
     constexpr int NW = NT / 64;
-    constexpr int CT0 = RB >= 4 ? 1 : sizeof(R) == 8 ? 4 / RB : (K == 16 ? 8 : 4);
-    constexpr int LK = LT > k ? LT - k : 0;     // column bits (instantiations with LT < k never run)
-    constexpr int NTILE = ((1 << LK) + 15) >> 4;
-    constexpr int CT = CT0 < NTILE / NW ? CT0 : NTILE / NW >= 1 ? NTILE / NW : 1;
+    constexpr int CT = block_ct(k, LT, sizeof(R) == 8);
+    static_assert(!GA || K <= AREG_MAX, "register fragments: blocks of up to 4 qubits");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int lb[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) lb[r] = op.lb[r];
-    uint32_t bmask = 0;
-#pragma unroll
-    for (int r = 0; r < k; ++r) bmask |= 1u << lb[r];
     auto scat = [&](int j) {                   // block row index -> tile bits
         uint32_t e = 0;
 #pragma unroll
@@ -250,8 +251,10 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     const int jlane = TT<R>::out_row(g, 0) >> 1;
     const int plane = TT<R>::out_row(g, 0) & 1;
     const uint32_t swo = ES * sw(scat(jlane));
-    // the lane's column inside a column tile
-    const uint32_t swl = ES * sw(dep32((uint32_t)(lane & 15), bmask));
+    // the lane's column inside a column tile: its four lane bits' slots
+    uint32_t swl = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) swl ^= ((lane >> i) & 1) ? tab[lay.lane() + i] : 0u;
     const R* __restrict__ Arow = ldsA + lane;
     // small blocks keep their A fragments in registers for the whole block
     // (the epilogue's LDS writes would otherwise force a re-read per column
@@ -260,7 +263,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     R afr[NA];
     if constexpr (K <= AREG_MAX) {
 #pragma unroll
-        for (int i = 0; i < NA; ++i) afr[i] = Arow[i * 64];
+        for (int i = 0; i < NA; ++i) afr[i] = GA ? fa[i] : Arow[i * 64];
     }
     for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
         uint32_t swe[CT];
@@ -441,9 +444,40 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     }
 }
 
+// Orders a wave's LDS accesses before and after it (a wave's LDS operations
+// execute in issue order, so this only stops the compiler from moving them
+// across): enough between two blocks in which every wave touches the same
+// tile elements.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A block's real A fragments for GA blocks: lane l's share, fragment (rb, s)
+// at index rb KS + s (k = 3: 4 values, k = 4: 16), read from the plan.
+template <typename R>
+__device__ __forceinline__ void fetch_frag(R (&dst)[NFA], const TOp& b, const char* __restrict__ blob) {
+    const R* __restrict__ f = (const R*)(blob + b.data) + (threadIdx.x & 63);
+    if (b.k == 3) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dst[i] = f[64 * i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NFA; ++i) dst[i] = f[64 * i];
+    }
+}
+
 // ---------------------------------------------------------------- kernel
 // The tile is read and written once per pass with nontemporal accesses (the
 // state streams through; caching it in L2 gains nothing).
+//
+// Passes whose blocks are all of 3 or 4 qubits keep every block's A
+// fragments in registers (fetched one block ahead) and need no LDS fragment
+// area; a workgroup barrier separates consecutive ops except blocks marked
+// BLK_NOSYNC, whose waves touch the same elements as in the block before.
+// Passes with wider blocks stage each block's fragments in LDS, with a
+// barrier after every op.
 template <typename R, int L>
 __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
@@ -487,6 +521,45 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     __syncthreads();
 
     const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
+    R fa[NFA];
+    if (pd.kmax <= 4) {
+        R fb[NFA];
+        if (pd.first_block >= 0) fetch_frag<R>(fa, ops[pd.first_block], blob);
+        bool first = true;           // the barrier after the load phase covers the first op
+        for (int oi = 0; oi < pd.nops; ++oi) {
+            const TOp& op = ops[oi];
+            if (op.type != TOP_BLOCK && (op.flags & DRUN_EPILOGUE)) continue;   // applied by the block before it
+            if (!first) {
+                if (op.type == TOP_BLOCK && (op.flags & BLK_NOSYNC)) wave_lds_order();
+                else __syncthreads();
+            }
+            first = false;
+            if (op.type == TOP_BLOCK) {
+                const int nb = op.next_block;
+                if (nb >= 0) fetch_frag<R>(fb, ops[nb], blob);
+                // a diagonal run right after the block may ride in its epilogue
+                constexpr bool RUNOK = sizeof(R) == 4 && L == 13;
+                const bool erun = RUNOK && (op.flags & BLK_RUN) != 0;
+                if (op.k == 3) {
+                    if (erun) tile_block<R, 16, L, RUNOK, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base);
+                    else tile_block<R, 16, L, false, true>(lds, ldsA, fa, op, blob, L);
+                } else {
+                    if (erun) tile_block<R, 32, L, RUNOK, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base);
+                    else tile_block<R, 32, L, false, true>(lds, ldsA, fa, op, blob, L);
+                }
+                if (nb >= 0) {
+#pragma unroll
+                    for (int i = 0; i < NFA; ++i) fa[i] = fb[i];
+                }
+            } else if (op.flags & DRUN_TURNS) {
+                tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data), (const uint32_t*)(blob + op.tab),
+                                         base, (op.flags & DRUN_SIGNS) != 0);
+            } else {
+                tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+            }
+        }
+        __syncthreads();
+    } else {
     // fragments: the first block's are copied to LDS with the tile (the
     // barrier below covers them); each later block's are read into
     // registers while the block before it runs and stored to LDS after it.
@@ -521,16 +594,16 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
             switch (op.k) {
                 case 3:
                     if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 16, L, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
-                    tile_block<R, 16, L>(lds, ldsA, op, blob, L);
+                        if (erun) { tile_block<R, 16, L, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 16, L>(lds, ldsA, fa, op, blob, L);
                     break;
                 case 4:
                     if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 32, L, true>(lds, ldsA, op, blob, L, &ops[oi + 1], base); break; }
-                    tile_block<R, 32, L>(lds, ldsA, op, blob, L);
+                        if (erun) { tile_block<R, 32, L, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base); break; }
+                    tile_block<R, 32, L>(lds, ldsA, fa, op, blob, L);
                     break;
-                case 5: tile_block<R, 64, L>(lds, ldsA, op, blob, L); break;
-                case 6: tile_block<R, 128, L>(lds, ldsA, op, blob, L); break;
+                case 5: tile_block<R, 64, L>(lds, ldsA, fa, op, blob, L); break;
+                case 6: tile_block<R, 128, L>(lds, ldsA, fa, op, blob, L); break;
                 default: break;
             }
             __syncthreads();
@@ -556,6 +629,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
             __syncthreads();
         }
+    }
     }
 
     // store: per batch, LDS reads first (optionally through the tile-bit
@@ -609,7 +683,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
 
 size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
     const size_t es = dt == QVM_C64 ? 4 : 8;          // bytes per real
-    const size_t K = kmax_block >= 3 ? (size_t)2 << kmax_block : 0;
+    // blocks of up to 4 qubits keep their fragments in registers
+    const size_t K = kmax_block >= 5 ? (size_t)2 << kmax_block : 0;
     return ((size_t)2 << L) * es + K * K * es;
 }
 

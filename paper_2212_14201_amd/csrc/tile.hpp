@@ -9,6 +9,10 @@
 
 namespace qvm {
 
+constexpr int kTileThreads = 512;    // threads per tile workgroup (8 waves)
+constexpr int kLogTileThreads = 9;
+static_assert(1 << kLogTileThreads == kTileThreads, "kLogTileThreads");
+
 enum TileOpType : int32_t { TOP_BLOCK = 1, TOP_DIAGRUN = 2 };
 
 constexpr size_t kTileLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
@@ -21,7 +25,9 @@ enum : int32_t {
 };
 // Block flags (TOp::flags of a TOP_BLOCK).
 enum : int32_t {
-    BLK_RUN = 1             // the next op is a DRUN_EPILOGUE run this block applies to its outputs
+    BLK_RUN = 1,            // the next op is a DRUN_EPILOGUE run this block applies to its outputs
+    BLK_NOSYNC = 2          // each wave touches exactly the tile elements it touched in the
+                            // block before (same wave bits): no workgroup barrier between them
 };
 
 struct TOp {
@@ -47,13 +53,20 @@ __host__ __device__ inline uint32_t tile_swizzle(uint32_t e) {
 // LDS slot times the bytes of one complex amplitude; the tile sits at the
 // start of LDS): the wave-uniform parts of the block's LDS addresses, so
 // that the kernel forms each address with one XOR per access (byte offsets
-// of slots are linear over GF(2) as well).
-//   col[ti], ti < ntile = ceil(2^(L-k) / 16): slot(deposit(16 ti)) over the
-//            tile bits outside the block (the column tile's base)
+// of slots are linear over GF(2) as well).  The block's columns are the
+// tile bits outside the block; the planner assigns them roles: four lane
+// bits (a lane's column l % 16), then the bits of the column-tile index ti.
+//   col[ti], ti < ntile = ceil(2^(L-k) / 16): slot of the column tile's
+//            base (its ti bits placed on their tile bits)
 //   brow[t], t < K/8:  slot(rows(4 t)), the input rows of k-step pair t
 //   erow[4 rb + r], rb < K/16, r < 4: slot of the output rows a lane's
 //            register r of row block rb holds, without the lane's own share
-// rows(j) places block row index j on the block's tile bits lb[].
+//   lane[i], i < 4: slot of lane bit i's tile bit (0 where the block has
+//            fewer than four column bits)
+// rows(j) places block row index j on the block's tile bits lb[].  Wave w
+// takes the column tiles ti = ct + CT (w + 8 j) (ct < CT, j = 0, 1, ...),
+// so the three ti bits above the CT bits are the wave's: when two blocks
+// put the same tile bits there, each wave touches the same elements in both.
 struct BlockTabLayout {
     int ntile, nb, ne;
     __host__ __device__ BlockTabLayout(int L, int k) {
@@ -65,12 +78,21 @@ struct BlockTabLayout {
     __host__ __device__ int col() const { return 0; }
     __host__ __device__ int brow() const { return ntile; }
     __host__ __device__ int erow() const { return ntile + nb; }
-    __host__ __device__ int words() const { return ntile + nb + ne; }
+    __host__ __device__ int lane() const { return ntile + nb + ne; }
+    __host__ __device__ int words() const { return ntile + nb + ne + 4; }
 };
 
-constexpr int kTileThreads = 512;    // threads per tile workgroup (8 waves)
-constexpr int kLogTileThreads = 9;
-static_assert(1 << kLogTileThreads == kTileThreads, "kLogTileThreads");
+// Column tiles a wave takes per iteration in the block kernel (K = 2^(k+1)
+// real rows): complex64 8 for k = 3, 4 for k = 4; complex128 4 / (K / 16);
+// 1 for k >= 5; at most the wave's share of the tile's column tiles.
+__host__ __device__ constexpr int block_ct(int k, int L, bool c128) {
+    const int K = 2 << k, RB = K / 16;
+    const int ct0 = RB >= 4 ? 1 : c128 ? 4 / RB : (K == 16 ? 8 : 4);
+    const int lk = L > k ? L - k : 0;
+    const int ntile = ((1 << lk) + 15) >> 4;
+    const int share = ntile / (kTileThreads / 64);
+    return ct0 < share ? ct0 : share >= 1 ? share : 1;
+}
 
 // One phase term of a diagonal run: amplitudes whose local tile bits match
 // (lmask, lval) and whose tile's outer bits match (omask, oval) are

@@ -274,34 +274,147 @@ def test_angle_path_encoding_reproduces_diagonal(dtype, n):
         assert np.max(np.abs(got - want)) < tol, (only_signs, np.max(np.abs(got - want)))
 
 
-def epilogue_elements(lb, k, L=13):
-    """Tile element held as (thread code, element code) by the epilogue of a
-    complex64 k-qubit block (k = 3, 4) in a 13-qubit tile: lane l, wave w,
-    column tile ct, row block rb and register pair hh hold column
-    (CT w + ct) 16 + l % 16 (the tile bits outside the block, ascending) and
-    block row 8 rb + 2 (l / 16) + hh."""
-    CT, LCT = (8, 3) if k == 3 else (4, 2)
-    free = [b for b in range(L) if b not in lb[:k]]
-    out = np.zeros((16, 512), np.int64)
-    for tc in range(512):
-        lane, w = tc & 63, tc >> 6
-        for ic in range(16):
-            hh, ct, rb = ic & 1, (ic >> 1) & (CT - 1), ic >> (1 + LCT)
-            col = (CT * w + ct) * 16 + (lane & 15)
-            row = 8 * rb + 2 * (lane >> 4) + hh
-            e = sum(((col >> m) & 1) << free[m] for m in range(len(free)))
-            e |= sum(((row >> r) & 1) << lb[r] for r in range(k))
-            out[ic, tc] = e
-    return out
+def _swz(e):
+    """The tile kernel's LDS swizzle (an involution: it is its own inverse)."""
+    e = np.asarray(e, dtype=np.int64)
+    return e ^ ((((e >> 4) ^ (e >> 8)) & 7) << 1)
+
+
+def _block_ct(k, L, c128):
+    K = 2 << k
+    RB = K // 16
+    ct0 = 1 if RB >= 4 else (4 // RB if c128 else (8 if K == 16 else 4))
+    ntile = ((1 << max(L - k, 0)) + 15) >> 4
+    share = ntile // 8
+    return ct0 if ct0 < share else (share if share >= 1 else 1)
+
+
+def block_layout(rec, op, L, dtype):
+    """Emulates how the tile kernel's block op forms its LDS addresses from
+    the op's address table (col, brow, erow, lane words).  Lanes l, l + 16,
+    l + 32, l + 48 of a wave share a column (l % 16) of each column tile the
+    wave takes; each lane reads its share of the column's complex input rows
+    and writes its share of the output rows.  Returns (inputs, outputs,
+    wave, epi): inputs[col, row] / outputs[col, row] are the tile elements
+    the column's row is read from / written to, wave[col] its wave, and epi
+    the complex64 epilogue's outputs as rows (thread code, element code
+    hh | ct << 1 | rb << (1 + log2 CT), tile element)."""
+    k = int(op["k"])
+    lb = [int(v) for v in op["lb"][:k]]
+    c128 = dtype == "c128"
+    es = 16 if c128 else 8
+    K = 2 << k
+    RB, KS = K // 16, K // 4
+    ncol = 1 << (L - k)
+    ntile = (ncol + 15) >> 4
+    nb, ne = K // 8, 4 * RB
+    CT = _block_ct(k, L, c128)
+    LCT = CT.bit_length() - 1
+    tab = rec(int(op["tab"]), np.dtype("<u4"), ntile + nb + ne + 4).astype(np.int64)
+    col, brow, erow, lanew = tab[:ntile], tab[ntile:ntile + nb], tab[ntile + nb:ntile + nb + ne], tab[-4:]
+    scat = lambda j: sum(((j >> q) & 1) << lb[q] for q in range(k))
+    el = lambda slot: _swz(slot // es)
+    # column items (wave, column tile, lane column), in the kernel's order
+    w_, ti_, c_ = [], [], []
+    for w in range(8):
+        t0 = w * CT
+        while t0 < ntile:
+            for ct in range(CT):
+                if t0 + ct < ntile:
+                    for c16 in range(16):
+                        if (t0 + ct) * 16 + c16 < ncol:
+                            w_.append(w)
+                            ti_.append(t0 + ct)
+                            c_.append(c16)
+            t0 += 8 * CT
+    w_, ti_, c_ = np.array(w_), np.array(ti_), np.array(c_)
+    ct_ = ti_ % CT
+    swl = np.zeros(len(c_), np.int64)
+    for i in range(4):
+        swl ^= np.where((c_ >> i) & 1, lanew[i], 0)
+    swe = swl ^ col[ti_]
+    ins = np.full((len(c_), 1 << k), -1, np.int64)
+    outs = np.full((len(c_), 1 << k), -1, np.int64)
+    epi = []
+    for g in range(4):
+        swg = es * int(_swz(scat(g)))
+        for t in range(KS // 2):
+            ins[:, 4 * t + g] = el(swe ^ brow[t] ^ swg)
+        if not c128:
+            swo = es * int(_swz(scat(2 * g)))
+            for rb in range(RB):
+                for hh in range(2):
+                    e = el(swe ^ swo ^ erow[4 * rb + hh])
+                    outs[:, 8 * rb + 2 * g + hh] = e
+                    epi.append(np.stack([w_ * 64 + 16 * g + c_, hh | ct_ << 1 | rb << (1 + LCT), e], 1))
+        else:
+            swo = es * int(_swz(scat(g >> 1)))
+            for rb in range(RB):
+                for r in range(4):
+                    row = 8 * rb + 2 * r + (g >> 1)
+                    e = el(swe ^ swo ^ erow[4 * rb + r])
+                    assert np.all((outs[:, row] == -1) | (outs[:, row] == e))   # re, im from lanes g, g ^ 1
+                    outs[:, row] = e
+    epi = np.concatenate(epi) if epi else np.zeros((0, 3), np.int64)
+    return ins, outs, w_, epi
+
+
+def check_block_layouts(plan, dtype):
+    """Every block op of every pass: each item reads and writes the same
+    tile elements, row r of its column on the block's bit lb[r]; the items
+    cover every tile element exactly once; and a block marked BLK_NOSYNC
+    gives every wave exactly the elements it had in the block before (so no
+    workgroup barrier is needed between them).  Returns the number of
+    blocks and of BLK_NOSYNC blocks."""
+    rec, passes = plan_image(plan)
+    nblk = nsync = 0
+    for pd in passes:
+        L = int(pd["L"])
+        prev = None
+        for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
+            if op["type"] != 1:
+                if not op["flags"] & 4:
+                    prev = None
+                continue
+            nblk += 1
+            k = int(op["k"])
+            lb = [int(v) for v in op["lb"][:k]]
+            ins, outs, waves, _ = block_layout(rec, op, L, dtype)
+            assert np.array_equal(ins, outs) and np.all(ins >= 0)
+            cols = ins
+            rowbits = np.array([sum(((j >> q) & 1) << lb[q] for q in range(k)) for j in range(1 << k)])
+            assert np.all((cols ^ cols[:, :1]) == rowbits[None, :])       # row r on the block's bits
+            assert np.array_equal(np.sort(cols.reshape(-1)), np.arange(1 << L))
+            owned = [frozenset(ins[waves == w].reshape(-1).tolist()) for w in range(8)]
+            if op["flags"] & 2:
+                nsync += 1
+                assert prev is not None and owned == prev, "BLK_NOSYNC block changes the waves' elements"
+            prev = owned
+    return nblk, nsync
+
+
+@pytest.mark.parametrize("k_max,tile,dtype", [(3, 13, "c64"), (4, 13, "c64"), (3, 12, "c64"), (4, 11, "c64"),
+                                              (3, 12, "c128"), (4, 12, "c128")])
+def test_block_layouts_and_wave_ownership(k_max, tile, dtype):
+    """The block ops' address tables of the 30-qubit workload's plans (and
+    of a random circuit): full coverage and the wave ownership that lets
+    consecutive blocks skip the workgroup barrier; most blocks of the
+    register-fragment passes do skip it."""
+    cfg = config_circuit("qft30")
+    plan = qvm.Plan(cfg["gates"], 30, dtype, k_max=k_max, tile_qubits=tile)
+    nblk, nsync = check_block_layouts(plan, dtype)
+    assert nsync >= nblk // 3, (nblk, nsync)
+    n, gates = random_planner_circuit(31, n_range=(26, 26), g_range=(300, 300))
+    check_block_layouts(qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile), dtype)
 
 
 @pytest.mark.parametrize("k_max", [3, 4])
 def test_epilogue_runs_reproduce_the_circuit(k_max):
     """Pins the encoding of diagonal runs that a complex64 block applies to
     its outputs (13-qubit tiles): emulating the single pass op by op from the
-    plan image (blocks as their matrices on their tile bits, runs from their
-    terms over the block epilogue's layout or the standalone layout) gives
-    the oracle's state of the whole circuit."""
+    plan image (blocks through their address tables and matrices, runs from
+    their terms over the block epilogue's layout or the standalone layout)
+    gives the oracle's state of the whole circuit."""
     n = 13
     rng = np.random.Generator(np.random.PCG64(4100 + k_max))
     gates = blocks_and_diagonals(n, 4100 + k_max)
@@ -318,15 +431,17 @@ def test_epilogue_runs_reproduce_the_circuit(k_max):
     tile = psi0[phys].copy()
     wmask = np.uint64(0xFFFFFFFF)
     t = np.arange(512, dtype=np.uint64)
-    nb, n_epi, prev = 0, 0, None
+    nb, n_epi, n_sync, prev = 0, 0, 0, None
     for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
         if op["type"] == 1:
             blk = plan.block(nb)
             nb += 1
-            lb = [int(v) for v in op["lb"][: int(op["k"])]]
             assert blk["k"] == op["k"]
-            oracle.apply_matrix(tile, n, blk["matrix"], lb)
-            prev = (op, lb)
+            n_sync += bool(op["flags"] & 2)
+            ins, outs, _, epi_map = block_layout(rec, op, n, "c64")
+            x = tile[ins]                               # columns of the block's input
+            tile[outs] = x @ np.asarray(blk["matrix"]).T
+            prev = (op, epi_map)
             continue
         if op["flags"] & 1:
             epi = bool(op["flags"] & 4)
@@ -337,7 +452,9 @@ def test_epilogue_runs_reproduce_the_circuit(k_max):
             if epi:
                 n_epi += 1
                 assert prev is not None and prev[0]["flags"] & 1
-                where = epilogue_elements(prev[1], int(prev[0]["k"]))
+                epi_map = prev[1]
+                where = np.full((16, 512), -1, np.int64)
+                where[epi_map[:, 1], epi_map[:, 0]] = epi_map[:, 2]
             else:
                 where = (np.arange(16)[:, None] * 512 + np.arange(512)[None, :])
             if op["flags"] & 2:
