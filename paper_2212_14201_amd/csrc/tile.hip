@@ -209,7 +209,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                                            const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
     static_assert(!RUN || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
-    const int L = RUN ? 13 : L_;              // LT, the kernel's tile width
+    constexpr int L = LT;                      // the kernel's tile width
+    (void)L_;
     using V4 = typename TT<R>::V4;
     constexpr int RB = K / 16;                 // 16-row blocks of the real matrix
     constexpr int KS = K / 4;                  // k-steps of 4 real rows
@@ -223,7 +224,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     constexpr int NW = NT / 64;
     constexpr int CT = block_ct(k, LT, sizeof(R) == 8);
     static_assert(!GA || K <= AREG_MAX, "register fragments: blocks of up to 4 qubits");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the wave index as a scalar, so the column table reads below are scalar loads
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int lb[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) lb[r] = op.lb[r];
@@ -234,8 +236,10 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
             if ((j >> q) & 1) e |= 1u << lb[q];
         return e;
     };
-    const int ncol = 1 << (L - k);
-    const int ntile = (ncol + 15) >> 4;
+    constexpr int ncol = L >= k ? 1 << (L - k) : 1;
+    constexpr int ntile = (ncol + 15) >> 4;
+    // every wave takes whole column tiles of full columns: no bounds tests
+    constexpr bool FULL = ncol >= 16 && ntile % (NW * CT) == 0;
     const int g = lane >> 4;
     // The slots are linear in the bits they are built from, so each address
     // is a wave-uniform part from the block's table (scalar loads) XOR a
@@ -271,8 +275,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int c = (t0 + ct) * 16 + (lane & 15);
-            ok[ct] = (t0 + ct) < ntile && c < ncol;
-            swe[ct] = ok[ct] ? swl ^ tab[lay.col() + min(t0 + ct, ntile - 1)] : 0u;
+            if constexpr (FULL) {
+                ok[ct] = true;
+                swe[ct] = swl ^ tab[lay.col() + t0 + ct];
+            } else {
+                ok[ct] = (t0 + ct) < ntile && c < ncol;
+                swe[ct] = ok[ct] ? swl ^ tab[lay.col() + min(t0 + ct, ntile - 1)] : 0u;
+            }
         }
         V4 acc[CT][RB];
 #pragma unroll
@@ -444,14 +453,13 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     }
 }
 
-// Orders a wave's LDS accesses before and after it (a wave's LDS operations
-// execute in issue order, so this only stops the compiler from moving them
-// across): enough between two blocks in which every wave touches the same
-// tile elements.
+// Orders a wave's LDS accesses before and after it: a wave's LDS operations
+// execute in issue order, so it is enough that the compiler moves no memory
+// access across (no wait for the writes before it is needed); used between
+// two blocks in which every wave touches the same tile elements.
 __device__ __forceinline__ void wave_lds_order() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    asm volatile("" ::: "memory");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // A block's real A fragments for GA blocks: lane l's share, fragment (rb, s)
