@@ -486,6 +486,7 @@ std::vector<uint32_t> block_table(const int32_t* lb, int k, int L, qvm_dtype dt,
             t[lay.erow() + 4 * rb + r] = j < 0 ? 0u : es * tile_swizzle(rows(j));
         }
     for (int i = 0; i < cm.nlane; ++i) t[lay.lane() + i] = es * tile_swizzle(1u << cm.lane[i]);
+    for (int r = 0; r < std::min(k, 4); ++r) t[lay.rbit() + r] = es * tile_swizzle(1u << lb[r]);
     return t;
 }
 
@@ -800,6 +801,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             }
             ops.push_back(op);
         };
+        // widest block of the pass (blocks are padded to 3 qubits)
+        int kmax_pass = 0;
+        for (const auto& u : pp.units)
+            if (u.block) kmax_pass = std::max(kmax_pass, std::max(3, (int)u.qubits.size()));
         for (auto& u : pp.units) {
             TOp op{};
             if (u.block) {
@@ -820,11 +825,17 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 for (int r = 0; r < k; ++r) op.lb[r] = local_of_wire[bq[r]];
                 if (image) {
                     M = block_matrix(G, u.gates, bq);
+                    // in a pass whose widest block has 4 qubits the kernel
+                    // fetches every block's fragments as 16 values per lane:
+                    // 3-qubit fragments are padded with zeros to that size
+                    const size_t pad = kmax_pass == 4 ? (size_t)16 * 64 : 0;
                     if (dt == QVM_C64) {
                         auto f = fragments<float>(M, k);
+                        if (f.size() < pad) f.resize(pad, 0.f);
                         op.data = B.put(f.data(), f.size() * sizeof(float));
                     } else {
                         auto f = fragments<double>(M, k);
+                        if (f.size() < pad) f.resize(pad, 0.0);
                         op.data = B.put(f.data(), f.size() * sizeof(double));
                     }
                 }
@@ -890,10 +901,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         // epoch; epilogue runs ride with their block.
         std::vector<uint32_t> wsel(ops.size(), 0u);
         {
-            int kmax_pass = 0;
+            int kmax_ops = 0;
             for (const TOp& o : ops)
-                if (o.type == TOP_BLOCK) kmax_pass = std::max(kmax_pass, (int)o.k);
-            if (kmax_pass <= 4) {
+                if (o.type == TOP_BLOCK) kmax_ops = std::max(kmax_ops, (int)o.k);
+            if (kmax_ops <= 4) {
                 const uint32_t tile_bits = (1u << L) - 1;
                 std::vector<size_t> members;
                 uint32_t allowed = 0;
@@ -971,6 +982,8 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 pd.kmax = std::max(pd.kmax, (int32_t)ops[oi].k);
             }
         }
+        if (pd.kmax != (pd.first_block >= 0 ? kmax_pass : pd.kmax))
+            return fail_plan(QVM_EARG, "internal: pass block width mismatch");
         pd.qmask = qmask;
         pd.ops = ops.empty() ? 0 : B.put(ops.data(), ops.size() * sizeof(TOp));
         std::vector<uint64_t> ldoff((size_t)1 << (L - c));

@@ -171,6 +171,31 @@ __device__ __forceinline__ void run_angles(TU (&acc)[1 << NHB], const DTerm* __r
             if ((i >> b) & 1) acc[i] += acc[i ^ (1 << b)];
 }
 
+// The tile kernel declares no static LDS, so its dynamic LDS (the tile
+// first) starts at LDS address 0 and a tile byte offset is an LDS address:
+// accesses through these take no base add.
+template <typename T>
+__device__ __forceinline__ T lds_ld(uint32_t off) {
+    return *(const __attribute__((address_space(3))) T*)(size_t)off;
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(uint32_t off, T v) {
+    *(__attribute__((address_space(3))) T*)(size_t)off = v;
+}
+
+// N uniform table words in one scalar load (dword alignment only).
+template <int N>
+__device__ __forceinline__ void sload(uint32_t (&dst)[N], const uint32_t* __restrict__ p) {
+    if constexpr (N == 1) {
+        dst[0] = p[0];
+    } else {
+        typedef uint32_t V __attribute__((ext_vector_type(N), aligned(4)));
+        const V v = *(const V*)p;
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[i] = v[i];
+    }
+}
+
 // ---------------------------------------------------------------- blocks
 // The block's real fragments are already in LDS (after the tile; the
 // kernel stages them while the previous op runs); every k-step reads one A
@@ -201,10 +226,8 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // With GA (blocks of up to 4 qubits in passes without wider blocks) the A
 // fragments come from the caller's registers (fetched from the plan one
 // block ahead) instead of the LDS fragment area.
-constexpr int NFA = 16;            // fragment registers per lane for GA blocks (k <= 4, complex64 or 128)
-
-template <typename R, int K, int LT, bool RUN = false, bool GA = false>
-__device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NFA],
+template <typename R, int K, int LT, bool RUN = false, bool GA = false, int NF = 1>
+__device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NF],
                                            const TOp& op, const char* __restrict__ blob, int L_,
                                            const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
     static_assert(!RUN || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
@@ -223,42 +246,46 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     // tiles keep every wave busy)
     constexpr int NW = NT / 64;
     constexpr int CT = block_ct(k, LT, sizeof(R) == 8);
-    static_assert(!GA || K <= AREG_MAX, "register fragments: blocks of up to 4 qubits");
+    static_assert(!GA || RB * KS <= NF, "register fragments: the block's share fits the registers");
     // the wave index as a scalar, so the column table reads below are scalar loads
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int lb[6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) lb[r] = op.lb[r];
-    auto scat = [&](int j) {                   // block row index -> tile bits
-        uint32_t e = 0;
-#pragma unroll
-        for (int q = 0; q < k; ++q)
-            if ((j >> q) & 1) e |= 1u << lb[q];
-        return e;
-    };
     constexpr int ncol = L >= k ? 1 << (L - k) : 1;
     constexpr int ntile = (ncol + 15) >> 4;
     // every wave takes whole column tiles of full columns: no bounds tests
     constexpr bool FULL = ncol >= 16 && ntile % (NW * CT) == 0;
     const int g = lane >> 4;
     // The slots are linear in the bits they are built from, so each address
-    // is a wave-uniform part from the block's table (scalar loads) XOR a
-    // per-lane part computed once here, all as byte offsets from the tile's
-    // start (LDS address 0), so an access takes one XOR and no add.
+    // is a per-lane part computed once here XOR a wave-uniform part from the
+    // block's table (scalar loads, combined on the scalar unit), as byte
+    // offsets from the tile's start (LDS address 0): one XOR per access.
     constexpr uint32_t ES = 2 * sizeof(R);     // bytes per amplitude
-    char* __restrict__ tb = (char*)lds;
+    (void)lds;
     const BlockTabLayout lay(L, k);
     const uint32_t* __restrict__ tab = (const uint32_t*)(blob + op.tab);
-    // B operand: complex input row 4 t + g; the lane's share is rows(g)
-    const uint32_t swg = ES * sw(scat(g));
-    // epilogue: the lane's share of the output row index
-    const int jlane = TT<R>::out_row(g, 0) >> 1;
-    const int plane = TT<R>::out_row(g, 0) & 1;
-    const uint32_t swo = ES * sw(scat(jlane));
+    // the block's uniform words that do not depend on the column tile,
+    // each group in one scalar load
+    constexpr int NBW = KS / 2, NEW = 4 * RB;
+    uint32_t lanew[4], rbit[4], bw[NBW], ew[NEW];
+    sload<4>(lanew, tab + lay.lane());
+    sload<4>(rbit, tab + lay.rbit());
+    sload<NBW>(bw, tab + lay.brow());
+    sload<NEW>(ew, tab + lay.erow());
     // the lane's column inside a column tile: its four lane bits' slots
     uint32_t swl = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) swl ^= ((lane >> i) & 1) ? tab[lay.lane() + i] : 0u;
+    for (int i = 0; i < 4; ++i) swl ^= ((lane >> i) & 1) ? lanew[i] : 0u;
+    auto rows_slot = [&](int j) {              // slot of block row index j < 8 (bits on lb[0..2])
+        uint32_t e = 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) e ^= ((j >> r) & 1) ? rbit[r] : 0u;
+        return e;
+    };
+    // B operand: complex input row 4 t + g; the lane's share is rows(g)
+    const uint32_t pin = swl ^ rows_slot(g);
+    // epilogue: the lane's share of the output row index
+    const int jlane = TT<R>::out_row(g, 0) >> 1;
+    const int plane = TT<R>::out_row(g, 0) & 1;
+    const uint32_t pout = swl ^ rows_slot(jlane);
     const R* __restrict__ Arow = ldsA + lane;
     // small blocks keep their A fragments in registers for the whole block
     // (the epilogue's LDS writes would otherwise force a re-read per column
@@ -270,19 +297,19 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
         for (int i = 0; i < NA; ++i) afr[i] = GA ? fa[i] : Arow[i * 64];
     }
     for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
-        uint32_t swe[CT];
+        uint32_t cw[CT];                       // column tiles' slots (uniform)
         bool ok[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int c = (t0 + ct) * 16 + (lane & 15);
             if constexpr (FULL) {
                 ok[ct] = true;
-                swe[ct] = swl ^ tab[lay.col() + t0 + ct];
             } else {
                 ok[ct] = (t0 + ct) < ntile && c < ncol;
-                swe[ct] = ok[ct] ? swl ^ tab[lay.col() + min(t0 + ct, ntile - 1)] : 0u;
+                cw[ct] = tab[lay.col() + min(t0 + ct, ntile - 1)];
             }
         }
+        if constexpr (FULL) sload<CT>(cw, tab + lay.col() + t0);
         V4 acc[CT][RB];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
@@ -291,10 +318,10 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
         using V2 = typename TT<R>::V2;
 #pragma unroll (K <= AREG_MAX ? KS / 2 : 2)
         for (int t = 0; t < KS / 2; ++t) {
-            const uint32_t st = tab[lay.brow() + t] ^ swg;
+            const uint32_t st = bw[t];
             V2 b[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? *(const V2*)(tb + (swe[ct] ^ st)) : V2{0, 0};
+            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds_ld<V2>(pin ^ (cw[ct] ^ st)) : V2{0, 0};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -327,7 +354,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                     // complex rows 8 rb + 2 g and 8 rb + 2 g + 1
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
-                        const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + hh];
+                        const uint32_t sl = pout ^ (cw[ct] ^ ew[4 * rb + hh]);
                         R yr = acc[ct][rb][2 * hh], yi = acc[ct][rb][2 * hh + 1];
                         if constexpr (RUN) {
                             const TU a = ang[(hh | ct << 1 | rb << (1 + LCT)) % NEC];
@@ -342,13 +369,13 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                                 yi = fr * yi + fi * xr;
                             }
                         }
-                        *(float2*)(tb + sl) = make_float2(yr, yi);
+                        lds_st<typename TT<R>::V2>(sl, typename TT<R>::V2{yr, yi});
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const uint32_t sl = swe[ct] ^ swo ^ tab[lay.erow() + 4 * rb + r];
-                        *(R*)(tb + (sl | (uint32_t)plane * sizeof(R))) = acc[ct][rb][r];
+                        const uint32_t sl = pout ^ (cw[ct] ^ ew[4 * rb + r]);
+                        lds_st<R>(sl | (uint32_t)plane * sizeof(R), acc[ct][rb][r]);
                     }
                 }
             }
@@ -463,17 +490,60 @@ __device__ __forceinline__ void wave_lds_order() {
 }
 
 // A block's real A fragments for GA blocks: lane l's share, fragment (rb, s)
-// at index rb KS + s (k = 3: 4 values, k = 4: 16), read from the plan.
-template <typename R>
-__device__ __forceinline__ void fetch_frag(R (&dst)[NFA], const TOp& b, const char* __restrict__ blob) {
+// at index rb KS + s, read from the plan.  Every block of a pass is fetched
+// with the same count NF (4 when all its blocks have 3 qubits, else 16: the
+// planner pads 3-qubit fragments of such passes to 16), so the loads in
+// flight are known at every point and waiting for one block's fragments
+// never waits for the next block's.
+template <typename R, int NF>
+__device__ __forceinline__ void fetch_frag(R (&dst)[NF], const TOp& b, const char* __restrict__ blob) {
     const R* __restrict__ f = (const R*)(blob + b.data) + (threadIdx.x & 63);
-    if (b.k == 3) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dst[i] = f[64 * i];
-    } else {
+    for (int i = 0; i < NF; ++i) dst[i] = f[64 * i];
+}
+
+// The ops of a pass whose blocks all have 3 or 4 qubits: fragments in
+// registers (fetched one block ahead), a workgroup barrier between ops
+// except before blocks marked BLK_NOSYNC.
+template <typename R, int L, int NF>
+__device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp* __restrict__ ops, const PassDesc& pd,
+                                                 const char* __restrict__ blob, uint64_t base) {
+    R fa[NF], fb[NF];
+    if (pd.first_block >= 0) fetch_frag<R, NF>(fa, ops[pd.first_block], blob);
+    bool first = true;           // the barrier after the load phase covers the first op
+    for (int oi = 0; oi < pd.nops; ++oi) {
+        const TOp& op = ops[oi];
+        if (op.type != TOP_BLOCK && (op.flags & DRUN_EPILOGUE)) continue;   // applied by the block before it
+        if (!first) {
+            if (op.type == TOP_BLOCK && (op.flags & BLK_NOSYNC)) wave_lds_order();
+            else __syncthreads();
+        }
+        first = false;
+        if (op.type == TOP_BLOCK) {
+            const int nb = op.next_block;
+            if (nb >= 0) fetch_frag<R, NF>(fb, ops[nb], blob);
+            // a diagonal run right after the block may ride in its epilogue
+            constexpr bool RUNOK = sizeof(R) == 4 && L == 13;
+            const bool erun = RUNOK && (op.flags & BLK_RUN) != 0;
+            if (NF == 4 || op.k == 3) {
+                if (erun) tile_block<R, 16, L, RUNOK, true>(lds, lds, fa, op, blob, L, &ops[oi + 1], base);
+                else tile_block<R, 16, L, false, true>(lds, lds, fa, op, blob, L);
+            } else if constexpr (NF >= 16) {
+                if (erun) tile_block<R, 32, L, RUNOK, true>(lds, lds, fa, op, blob, L, &ops[oi + 1], base);
+                else tile_block<R, 32, L, false, true>(lds, lds, fa, op, blob, L);
+            }
+            if (nb >= 0) {
 #pragma unroll
-        for (int i = 0; i < NFA; ++i) dst[i] = f[64 * i];
+                for (int i = 0; i < NF; ++i) fa[i] = fb[i];
+            }
+        } else if (op.flags & DRUN_TURNS) {
+            tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data), (const uint32_t*)(blob + op.tab), base,
+                                     (op.flags & DRUN_SIGNS) != 0);
+        } else {
+            tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+        }
     }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- kernel
@@ -529,45 +599,12 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     __syncthreads();
 
     const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
-    R fa[NFA];
-    if (pd.kmax <= 4) {
-        R fb[NFA];
-        if (pd.first_block >= 0) fetch_frag<R>(fa, ops[pd.first_block], blob);
-        bool first = true;           // the barrier after the load phase covers the first op
-        for (int oi = 0; oi < pd.nops; ++oi) {
-            const TOp& op = ops[oi];
-            if (op.type != TOP_BLOCK && (op.flags & DRUN_EPILOGUE)) continue;   // applied by the block before it
-            if (!first) {
-                if (op.type == TOP_BLOCK && (op.flags & BLK_NOSYNC)) wave_lds_order();
-                else __syncthreads();
-            }
-            first = false;
-            if (op.type == TOP_BLOCK) {
-                const int nb = op.next_block;
-                if (nb >= 0) fetch_frag<R>(fb, ops[nb], blob);
-                // a diagonal run right after the block may ride in its epilogue
-                constexpr bool RUNOK = sizeof(R) == 4 && L == 13;
-                const bool erun = RUNOK && (op.flags & BLK_RUN) != 0;
-                if (op.k == 3) {
-                    if (erun) tile_block<R, 16, L, RUNOK, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base);
-                    else tile_block<R, 16, L, false, true>(lds, ldsA, fa, op, blob, L);
-                } else {
-                    if (erun) tile_block<R, 32, L, RUNOK, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base);
-                    else tile_block<R, 32, L, false, true>(lds, ldsA, fa, op, blob, L);
-                }
-                if (nb >= 0) {
-#pragma unroll
-                    for (int i = 0; i < NFA; ++i) fa[i] = fb[i];
-                }
-            } else if (op.flags & DRUN_TURNS) {
-                tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data), (const uint32_t*)(blob + op.tab),
-                                         base, (op.flags & DRUN_SIGNS) != 0);
-            } else {
-                tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
-            }
-        }
-        __syncthreads();
+    if (pd.kmax <= 3) {
+        tile_ops_regfrag<R, L, 4>(lds, ops, pd, blob, base);
+    } else if (pd.kmax == 4) {
+        tile_ops_regfrag<R, L, 16>(lds, ops, pd, blob, base);
     } else {
+    R fa[1];                     // unused: wider passes read fragments from LDS
     // fragments: the first block's are copied to LDS with the tile (the
     // barrier below covers them); each later block's are read into
     // registers while the block before it runs and stored to LDS after it.

@@ -63,6 +63,7 @@ __host__ __device__ inline uint32_t tile_swizzle(uint32_t e) {
 //            register r of row block rb holds, without the lane's own share
 //   lane[i], i < 4: slot of lane bit i's tile bit (0 where the block has
 //            fewer than four column bits)
+//   rbit[r], r < 4: slot of block bit r's tile bit (0 for r >= k)
 // rows(j) places block row index j on the block's tile bits lb[].  Wave w
 // takes the column tiles ti = ct + CT (w + 8 j) (ct < CT, j = 0, 1, ...),
 // so the three ti bits above the CT bits are the wave's: when two blocks
@@ -79,7 +80,8 @@ struct BlockTabLayout {
     __host__ __device__ int brow() const { return ntile; }
     __host__ __device__ int erow() const { return ntile + nb; }
     __host__ __device__ int lane() const { return ntile + nb + ne; }
-    __host__ __device__ int words() const { return ntile + nb + ne + 4; }
+    __host__ __device__ int rbit() const { return ntile + nb + ne + 4; }
+    __host__ __device__ int words() const { return ntile + nb + ne + 8; }
 };
 
 // Column tiles a wave takes per iteration in the block kernel (K = 2^(k+1)
