@@ -45,7 +45,7 @@ template <> struct TT<float> {
     using V16 = f32v4;                // one 16-byte access: two complex64
     static constexpr int EP = 2;      // elements per 16-byte access
     static constexpr int C = 4;       // low bits per tile: 16 x 8 B = 128-byte runs
-    static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
+    static __host__ __device__ constexpr int out_row(int g, int r) { return 4 * g + r; }
 };
 template <> struct TT<double> {
     using V4 = f64x4;
@@ -53,7 +53,7 @@ template <> struct TT<double> {
     using V16 = f64v2;                // one 16-byte access: one complex128
     static constexpr int EP = 1;
     static constexpr int C = 3;       // low bits per tile: 8 x 16 B = 128-byte runs
-    static __device__ __forceinline__ int out_row(int g, int r) { return g + 4 * r; }
+    static __host__ __device__ constexpr int out_row(int g, int r) { return g + 4 * r; }
 };
 
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
@@ -256,8 +256,9 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     const int g = lane >> 4;
     // The slots are linear in the bits they are built from, so each address
     // is a per-lane part computed once here XOR a wave-uniform part from the
-    // block's table (scalar loads, combined on the scalar unit), as byte
-    // offsets from the tile's start (LDS address 0): one XOR per access.
+    // block's table (scalar loads, combined on the scalar unit: the
+    // readfirstlane below only tells the compiler the value is uniform), as
+    // byte offsets from the tile's start (LDS address 0): one XOR per access.
     constexpr uint32_t ES = 2 * sizeof(R);     // bytes per amplitude
     (void)lds;
     const BlockTabLayout lay(L, k);
@@ -270,22 +271,28 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     sload<4>(rbit, tab + lay.rbit());
     sload<NBW>(bw, tab + lay.brow());
     sload<NEW>(ew, tab + lay.erow());
+    // lane-bit masks (all ones where bit i of the lane index is set): each
+    // conditional slot below is one AND-XOR of a mask and a table word
+    auto lmask = [&](int i) { return 0u - (((uint32_t)lane >> i) & 1u); };
     // the lane's column inside a column tile: its four lane bits' slots
     uint32_t swl = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) swl ^= ((lane >> i) & 1) ? lanew[i] : 0u;
-    auto rows_slot = [&](int j) {              // slot of block row index j < 8 (bits on lb[0..2])
-        uint32_t e = 0;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) e ^= ((j >> r) & 1) ? rbit[r] : 0u;
-        return e;
-    };
-    // B operand: complex input row 4 t + g; the lane's share is rows(g)
-    const uint32_t pin = swl ^ rows_slot(g);
-    // epilogue: the lane's share of the output row index
-    const int jlane = TT<R>::out_row(g, 0) >> 1;
+    for (int i = 0; i < 4; ++i) swl ^= lanew[i] & lmask(i);
+    // B operand: complex input row 4 t + g (g = lane bits 4, 5 on block
+    // bits 0, 1); the lane's share is rows(g)
+    uint32_t pin = swl ^ (rbit[0] & lmask(4)) ^ (rbit[1] & lmask(5));
+    // epilogue: the lane's share of the output row index, rows(jlane):
+    // complex64 jlane = 2 g (block bits 1, 2), complex128 jlane = g >> 1
+    // (block bit 0; g & 1 picks the real or imaginary part)
+    constexpr bool F32 = TT<R>::EP == 2;
+    static_assert((TT<R>::out_row(1, 0) >> 1) == (F32 ? 2 : 0) && (TT<R>::out_row(2, 0) >> 1) == (F32 ? 4 : 1),
+                  "output row layout");
     const int plane = TT<R>::out_row(g, 0) & 1;
-    const uint32_t pout = swl ^ rows_slot(jlane);
+    uint32_t pout = F32 ? swl ^ (rbit[1] & lmask(4)) ^ (rbit[2] & lmask(5)) : swl ^ (rbit[0] & lmask(5));
+    // opaque copies: each access then takes one XOR of these with a scalar
+    // (the compiler would otherwise re-split them into their parts)
+    asm volatile("" : "+v"(pin));
+    asm volatile("" : "+v"(pout));
     const R* __restrict__ Arow = ldsA + lane;
     // small blocks keep their A fragments in registers for the whole block
     // (the epilogue's LDS writes would otherwise force a re-read per column
@@ -321,7 +328,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
             const uint32_t st = bw[t];
             V2 b[CT];
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) b[ct] = ok[ct] ? lds_ld<V2>(pin ^ (cw[ct] ^ st)) : V2{0, 0};
+            for (int ct = 0; ct < CT; ++ct)
+                b[ct] = ok[ct] ? lds_ld<V2>(pin ^ __builtin_amdgcn_readfirstlane(cw[ct] ^ st)) : V2{0, 0};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -354,7 +362,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                     // complex rows 8 rb + 2 g and 8 rb + 2 g + 1
 #pragma unroll
                     for (int hh = 0; hh < 2; ++hh) {
-                        const uint32_t sl = pout ^ (cw[ct] ^ ew[4 * rb + hh]);
+                        const uint32_t sl = pout ^ __builtin_amdgcn_readfirstlane(cw[ct] ^ ew[4 * rb + hh]);
                         R yr = acc[ct][rb][2 * hh], yi = acc[ct][rb][2 * hh + 1];
                         if constexpr (RUN) {
                             const TU a = ang[(hh | ct << 1 | rb << (1 + LCT)) % NEC];
@@ -374,7 +382,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const uint32_t sl = pout ^ (cw[ct] ^ ew[4 * rb + r]);
+                        const uint32_t sl = pout ^ __builtin_amdgcn_readfirstlane(cw[ct] ^ ew[4 * rb + r]);
                         lds_st<R>(sl | (uint32_t)plane * sizeof(R), acc[ct][rb][r]);
                     }
                 }
