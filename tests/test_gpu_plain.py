@@ -67,6 +67,33 @@ def test_many_controls_and_every_target_position(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 4, 5, 11])
+def test_phases_with_conditions_inside_a_line(n, dtype):
+    """Phase gates whose condition bits include the bits inside a 128-byte
+    line (qubits 0..2 for complex128, 0..3 for complex64) take the
+    line-granular kernel: every combination of low qubits, alone, with each
+    other and with a high qubit, controlled or not, on a random state."""
+    rng = np.random.default_rng(40 + n)
+    gates = [Gate("h", (q,)) for q in range(n)] + [Gate("u3", (q,), (), tuple(rng.uniform(0, 6, 3))) for q in range(n)]
+    low = [q for q in range(min(4, n))]
+    for a in low:
+        th = float(rng.uniform(0, 6))
+        gates += [Gate("z", (a,)), Gate("s", (a,)), Gate("t", (a,)), Gate("p", (a,), (), (th,))]
+        for b in range(n):
+            if b != a:
+                gates += [Gate("z", (b,), (a,)), Gate("p", (a,), (b,), (float(rng.uniform(0, 6)),))]
+        if n >= 3:
+            others = [q for q in range(n) if q != a]
+            c = tuple(int(q) for q in rng.choice(others, 2, replace=False))
+            gates.append(Gate("p", (a,), c, (th,)))
+    sv = run_gpu(n, gates, dtype)
+    want = oracle.simulate(n, gates)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    print(f"n={n} {dtype} {len(gates)} gates err {err:.2e}")
+    assert err <= tol(dtype, gates)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_three_qubit_unitaries_unsorted_targets(dtype):
     n = 12
     gates = random_mixed_circuit(n, 40, 77, kmax=3, max_ctrl=3, names=["unitary", "swap", "rzz"])
