@@ -24,6 +24,7 @@ def main():
     ap.add_argument("--qubits", type=int, nargs=2, default=(0, 1), help="phase: the CZ's control and target")
     ap.add_argument("--k", type=int, default=4, help="blocks: block width in qubits")
     ap.add_argument("--blocks", type=int, default=32, help="blocks: fused blocks in the one tile pass")
+    ap.add_argument("--tile", type=int, default=13, help="blocks: tile qubits of the pass")
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--launches", type=int, default=3)
@@ -70,7 +71,7 @@ def main():
         print(f"tile pass complex64 (one CZ): {ms:.3f} ms, {2 * 8 * 2**a.n / ms / 1e6:.0f} GB/s", flush=True)
         return
     if a.kernel == "blocks":
-        # one complex64 tile pass (13-qubit tiles) holding `blocks` random
+        # one complex64 tile pass (tiles of `tile` qubits) holding `blocks` random
         # k-qubit unitaries on overlapping windows of the tile qubits (so
         # that none fuse): the block kernel's cost in isolation
         import numpy as np
@@ -79,10 +80,10 @@ def main():
         for i in range(a.blocks):
             z = rng.standard_normal((2 ** a.k, 2 ** a.k)) + 1j * rng.standard_normal((2 ** a.k, 2 ** a.k))
             q, r = np.linalg.qr(z)
-            lo = i % (13 - a.k + 1)
+            lo = i % (a.tile - a.k + 1)
             gates.append(Gate("unitary", tuple(range(lo, lo + a.k)), (), (), -1, q))
         sv = qvm.StateVector(a.n, "c64", init=0)
-        plan = qvm.Plan(gates, a.n, "c64", k_max=a.k, tile_qubits=13)
+        plan = qvm.Plan(gates, a.n, "c64", k_max=a.k, tile_qubits=a.tile)
         assert plan.stats()["passes"] == 1 and plan.stats()["blocks"] == a.blocks
         for _ in range(a.launches):
             sv.init_basis(0)
