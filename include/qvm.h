@@ -339,9 +339,10 @@ qvm_status qvm_run_plan(qvm_sv* sv, const qvm_plan* plan);
  * the blocks' gates (before padding), 18 log2 state bytes, 19 log2 tile
  * count, 20 diagonal runs and 21 phase terms that take the angle-
  * accumulating path (standalone or in the epilogue of the block before
- * them).  out needs cap >= n_passes * QVM_PASS_FEATURES floats
- * (NULL: only *n_passes is set). */
-#define QVM_PASS_FEATURES 22
+ * them), 22 workgroup barriers between the pass's ops.  out needs
+ * cap >= n_passes * QVM_PASS_FEATURES floats (NULL: only *n_passes is
+ * set). */
+#define QVM_PASS_FEATURES 23
 qvm_status qvm_plan_pass_features(const qvm_plan* plan, float* out, size_t cap,
                                   int32_t* n_passes);
 
@@ -372,6 +373,14 @@ qvm_status qvm_simplify(const qvm_gate* in, size_t n_in, int n_qubits, qvm_gate*
                         size_t* n_out);
 
 /* ------------------------------------------------------------- gradients */
+
+/* Number of gate groups qvm_adjoint_expect_grad splits a circuit into (each
+ * group is one pass over the batch forward and one in reverse; up to 4
+ * target qubits per group for complex64, 3 for complex128), for callers
+ * that account for the passes the sweep executes.  Same gate, parameter
+ * index and error rules as qvm_adjoint_expect_grad.  Host-only. */
+qvm_status qvm_adjoint_group_count(int n_qubits, qvm_dtype dt, const qvm_gate* gates, size_t n_gates,
+                                   const int32_t* param_index, int n_params, int32_t* n_groups);
 
 /* Bytes of device workspace qvm_adjoint_expect_grad needs. */
 size_t qvm_adjoint_workspace_bytes(int n_qubits, int batch, size_t n_gates);

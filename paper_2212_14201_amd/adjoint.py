@@ -23,6 +23,9 @@ def _declare():
                                                  ctypes.c_size_t, _u64p, _u64p, _dp, _vp, _vp, _vp,
                                                  _dp, _dp]
     L.qvm_adjoint_expect_grad_static.restype = ctypes.c_int
+    L.qvm_adjoint_group_count.argtypes = [ctypes.c_int, ctypes.c_int, _gp, ctypes.c_size_t, _i32p,
+                                          ctypes.c_int, _i32p]
+    L.qvm_adjoint_group_count.restype = ctypes.c_int
     return L
 
 
@@ -54,6 +57,15 @@ class AdjointProblem:
             L = _declare()
             self.work = torch.empty(int(L.qvm_adjoint_workspace_bytes(self.n, self.batch, self.gates.n)),
                                     dtype=torch.uint8, device=self.device)
+
+    def group_count(self):
+        """Gate groups of the sweep: one pass over the batch each, forward
+        and in reverse."""
+        out = ctypes.c_int32()
+        check(_declare().qvm_adjoint_group_count(self.n, _dt(self.dtype), self.gates.ptr(), self.gates.n,
+                                                 self.pidx.ctypes.data_as(_i32p), self.n_params,
+                                                 ctypes.byref(out)))
+        return int(out.value)
 
     def run(self, params, want_grad=True):
         """params: array [batch, n_params].  Returns (f[batch], grad[batch, n_params] or None)."""

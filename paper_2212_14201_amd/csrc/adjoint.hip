@@ -379,6 +379,11 @@ std::vector<HostGroup> adj_groups(const std::vector<AdjGate>& G, int n, int r) {
     return out;
 }
 
+// Slots (target qubits) per gate group: complex64 holds 2 x 16 amplitudes
+// per thread (160 VGPRs), complex128 2 x 8 (four slots would take all 256
+// and leave one wave per SIMD).
+int adj_slots(int n, qvm_dtype dt) { return std::min(dt == QVM_C64 ? 4 : 3, n); }
+
 }  // namespace
 
 template <typename R>
@@ -425,9 +430,7 @@ static qvm_status adjoint_t(int n, int batch, const std::vector<AdjGate>& G, int
     double* res = (double*)(work + L.res_off);
     AdjOpDev* dops = (AdjOpDev*)(work + L.ops_off);
     // gate groups and their op table; gradient rows follow the group order
-    // complex64 holds 2 x 16 amplitudes per thread (160 VGPRs), complex128
-    // 2 x 8 (four slots would take all 256 and leave one wave per SIMD)
-    const int r = std::min(sizeof(R) == 4 ? 4 : 3, n);
+    const int r = adj_slots(n, sizeof(R) == 4 ? QVM_C64 : QVM_C128);
     std::vector<HostGroup> groups = adj_groups(G, n, r);
     std::vector<AdjOpDev> optab;
     std::vector<int> row_gate;        // gradient row (from 1) -> gate
@@ -619,6 +622,20 @@ qvm_status adj_scratch(char** out) {
 using namespace qvm;
 
 extern "C" {
+
+qvm_status qvm_adjoint_group_count(int n, qvm_dtype dt, const qvm_gate* gates, size_t n_gates,
+                                   const int32_t* param_index, int n_params, int32_t* n_groups) {
+    if (dt != QVM_C64 && dt != QVM_C128) return adj_fail(QVM_EARG, "unknown dtype");
+    if (!n_groups) return adj_fail(QVM_EARG, "NULL output");
+    std::vector<AdjGate> G;
+    std::vector<PauliTerms> terms;
+    const uint64_t z = 0;
+    const double c = 0;
+    qvm_status st = adj_prepare(n, 1, gates, n_gates, param_index, n_params, 1, &z, &z, &c, G, terms);
+    if (st) return st;
+    *n_groups = (int32_t)adj_groups(G, n, adj_slots(n, dt)).size();
+    return QVM_OK;
+}
 
 size_t qvm_adjoint_workspace_bytes(int n_qubits, int batch, size_t n_gates) {
     (void)n_qubits;

@@ -1129,6 +1129,23 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             f[17] = (float)ktrue;
             f[18] = (float)(n + (dt == QVM_C64 ? 3 : 4));     // log2 of state bytes
             f[19] = (float)(n - L);                           // log2 of the tile count
+            {
+                // workgroup barriers between the pass's ops (tile.hip):
+                // register-fragment passes skip them before BLK_NOSYNC
+                // blocks; passes with wider blocks take one after every op
+                // and one more per staged block fragment
+                int bars = 0, execd = 0;
+                for (const TOp& o : ops) {
+                    if (o.type != TOP_BLOCK && (o.flags & DRUN_EPILOGUE)) continue;
+                    if (pd.kmax <= 4) {
+                        if (execd && !(o.type == TOP_BLOCK && (o.flags & BLK_NOSYNC))) ++bars;
+                    } else {
+                        bars += o.type == TOP_BLOCK ? 2 : 1;
+                    }
+                    ++execd;
+                }
+                f[22] = (float)bars;
+            }
             P->pass_features.insert(P->pass_features.end(), f, f + QVM_PASS_FEATURES);
         }
         P->passes.push_back(pd);

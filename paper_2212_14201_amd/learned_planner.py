@@ -39,7 +39,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 from . import qvm  # noqa: E402
 from .qvm import _i32p, _vp, check, lib  # noqa: E402
 
-NFEAT = 22
+NFEAT = 23
 # the trained cost model shipped with the package (complex64 pass timings)
 DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "costmodel_c64.npz")
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
@@ -146,38 +146,51 @@ LONG_CIRCUIT = 600
 
 # ------------------------------------------------------------------ collect
 def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_range=(100, 500), mix=True):
-    """Time one random candidate plan per circuit; save every pass's features
-    and measured milliseconds (npz: features, ms, seed, cand).  mix: circuits
-    from the mixture of families (``workloads.planner_mix_circuit``), else
-    the random planner workload with the given ranges."""
+    """Time candidate plans of each circuit; save every pass's features and
+    measured milliseconds (npz: features, ms, seed, cand).  Each circuit
+    draws a setting at random: a tile width, whose candidates at every block
+    width are all timed (their pass i holds the same gates, so the model
+    learns the per-pass width choice from paired samples), or one block-per-
+    pass candidate.  mix: circuits from the mixture of families
+    (``workloads.planner_mix_circuit``), else the random planner workload
+    with the given ranges."""
     from workloads import planner_mix_circuit
     rng = np.random.Generator(np.random.PCG64(seed + first))
-    tiles = [c for c in CANDIDATES if c[0] == "tile"]
+    tile_ls = sorted({c[2] for c in CANDIDATES if c[0] == "tile"}, reverse=True)
+    blocks = [c for c in CANDIDATES if c[0] == "block"]
     jobs = []
     for s in range(first, first + count):
         if mix:
             n, gates, _ = planner_mix_circuit(s)
         else:
             n, gates = planner_circuit(s, n_range, g_range)
-        pool = tiles if len(gates) > LONG_CIRCUIT else CANDIDATES
-        jobs.append((n, s, gates, pool[int(rng.integers(0, len(pool)))]))
+        # tile settings three times as often as block settings; long
+        # circuits take tile settings only (one block per pass would take
+        # seconds per circuit; a block pass looks the same in either)
+        if len(gates) > LONG_CIRCUIT or rng.random() < 0.75:
+            L = tile_ls[int(rng.integers(0, len(tile_ls)))]
+            cands = [c for c in CANDIDATES if c[0] == "tile" and c[2] == L]
+        else:
+            cands = [blocks[int(rng.integers(0, len(blocks)))]]
+        jobs.append((n, s, gates, cands))
     jobs.sort(key=lambda j: j[0])          # group by size to reuse the state buffer
     pool = StatePool()
     F, T, S, C = [], [], [], []
     t0 = time.time()
-    for i, (n, s, gates, cand) in enumerate(jobs):
+    for i, (n, s, gates, cands) in enumerate(jobs):
         ga = qvm.GateArray(gates)
-        plan = build_plan(ga, n, dtype, cand)
-        if plan is None:
-            cand = ("block", 3, 0)
+        for cand in cands:
             plan = build_plan(ga, n, dtype, cand)
-        sv = pool.get(n, dtype)
-        _, ms = time_plan(sv, plan)
-        feats = plan_features(plan)
-        F.append(feats)
-        T.append(ms)
-        S.append(np.full(len(ms), s, dtype=np.int32))
-        C.append(np.full(len(ms), CANDIDATES.index(cand), dtype=np.int32))
+            if plan is None:
+                cand = ("block", 3, 0)
+                plan = build_plan(ga, n, dtype, cand)
+            sv = pool.get(n, dtype)
+            _, ms = time_plan(sv, plan)
+            feats = plan_features(plan)
+            F.append(feats)
+            T.append(ms)
+            S.append(np.full(len(ms), s, dtype=np.int32))
+            C.append(np.full(len(ms), CANDIDATES.index(cand), dtype=np.int32))
         if (i + 1) % 100 == 0:
             print(f"collect: {i + 1}/{len(jobs)} circuits, {sum(len(t) for t in T)} passes, "
                   f"{time.time() - t0:.0f} s", flush=True)
@@ -189,10 +202,14 @@ def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_ran
 
 
 # -------------------------------------------------------------------- model
+ADAPTIVE_MARGIN = 0.03
+
+
 class LearnedPlanner:
-    def __init__(self, net, mu, sd, lo=None, hi=None):
+    def __init__(self, net, mu, sd, lo=None, hi=None, adaptive_margin=ADAPTIVE_MARGIN):
         self.net, self.mu, self.sd = net, mu, sd
         self.lo, self.hi = lo, hi
+        self.adaptive_margin = adaptive_margin
 
     def predict_pass_ms(self, feats):
         """Predicted ms per pass.  Features are clamped to the range seen in
@@ -244,7 +261,10 @@ class LearnedPlanner:
             pick = P.argmin(axis=0)
             ks = [group[i][1] for i in pick]
             options.append((float(P.min(axis=0).sum()), ("adaptive", max(ks), L), ks))
-        pred, cand, ks = min(options, key=lambda t: t[0])
+        # the per-pass minimum over several predictions is biased low by the
+        # model's error: an adaptive plan must beat the fixed settings by a
+        # margin to be taken
+        pred, cand, ks = min(options, key=lambda t: t[0] * (1.0 + self.adaptive_margin if t[2] else 1.0))
         plan = build_plan(ga, n, dtype, cand, k_of_pass=ks)
         plan.k_of_pass = ks
         return cand, plan, pred

@@ -155,3 +155,33 @@ def test_one_hip_runtime_in_process():
     assert out.returncode == 0, out.stderr
     libs = eval(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1, libs
+
+
+def test_adjoint_group_count_host_only():
+    """qvm_adjoint_group_count (host-only): gates on one target form one
+    group; the 20-qubit ansatz needs at least five groups (20 targets, at
+    most four per complex64 group, three per complex128 one) and at most one
+    per gate; invalid gates are rejected."""
+    adj = pytest.importorskip("paper_2212_14201_amd.adjoint")
+    from workloads import hardware_efficient_ansatz
+    from paper_2212_14201_amd.qvm import GateArray, _dt, _gp, _i32p
+    import ctypes
+
+    def count(n, gates, n_params, dtype="c64"):
+        L = adj._declare()
+        ga = GateArray(gates)
+        pidx = np.ascontiguousarray([getattr(g, "pidx", -1) for g in gates], dtype=np.int32)
+        out = ctypes.c_int32()
+        st = L.qvm_adjoint_group_count(n, _dt(dtype), ga.ptr(), ga.n, pidx.ctypes.data_as(_i32p), n_params,
+                                       ctypes.byref(out))
+        return st, out.value
+
+    one = [Gate("ry", (3,), (), (0.0,), pidx=i) for i in range(10)]
+    assert count(6, one, 10) == (0, 1)
+    gates, P = hardware_efficient_ansatz(20, 16)
+    st, g64 = count(20, gates, P)
+    st2, g128 = count(20, gates, P, "c128")
+    assert st == 0 and st2 == 0
+    assert 5 <= g64 <= len(gates) and g64 <= g128 <= len(gates)   # 20 targets, at most 4 per group
+    bad = [Gate("h", (25,))]
+    assert count(20, bad, 0)[0] != 0
