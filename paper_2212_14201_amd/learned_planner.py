@@ -17,7 +17,9 @@ HIP events of the tile kernel), on a seeded mixture of circuit families
 CZ, Toffoli}, layered U3 + CZ bricks, QFT prefixes, rotation + CNOT layers;
 26-32 qubits).  Features are clamped to the training range when predicting.
 
-    python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 2000 --out D.npz
+    python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 2000 --no-mix --out R.npz
+    python -m paper_2212_14201_amd.learned_planner collect  --first 0 --count 1000 --out X.npz
+    python -m paper_2212_14201_amd.learned_planner combine  --data R.npz X.npz --out D.npz
     python -m paper_2212_14201_amd.learned_planner train    --data D.npz --model M.npz
     python -m paper_2212_14201_amd.learned_planner evaluate --model M.npz --first 100000 --count 200
     python -m paper_2212_14201_amd.learned_planner explain  --model M.npz --workload qft30
@@ -201,6 +203,40 @@ def collect(first, count, out_path, dtype="c64", seed=0, n_range=(26, 32), g_ran
     return sum(len(t) for t in T)
 
 
+def refeature(in_path, out_path, mix=False, n_range=(26, 32), g_range=(100, 500), dtype="c64"):
+    """Recompute the pass features of collected timings with the current
+    planner (host only): each (circuit seed, candidate) group of rows is
+    planned again for scoring and its features replace the stored ones.  The
+    timings stay valid as long as the kernels are unchanged; the schedule
+    must match pass for pass (same pass count, same features in the columns
+    both layouts share)."""
+    from workloads import planner_mix_circuit
+    z = np.load(in_path, allow_pickle=False)
+    F, T, S, C = z["features"], z["ms"], z["seed"], z["cand"]
+    out = np.zeros((len(F), NFEAT), dtype=np.float32)
+    shared = min(F.shape[1], NFEAT)
+    i = 0
+    while i < len(F):
+        j = i
+        while j < len(F) and S[j] == S[i] and C[j] == C[i] and (j == i or F[j, 0] == F[i, 0]):
+            j += 1
+        seed, cand = int(S[i]), CANDIDATES[int(C[i])]
+        if mix:
+            n, gates, _ = planner_mix_circuit(seed)
+        else:
+            n, gates = planner_circuit(seed, n_range, g_range)
+        plan = build_plan(qvm.GateArray(gates), n, dtype, cand, image=False)
+        f = plan_features(plan)
+        # a group may hold several timed runs of one candidate back to back
+        reps = (j - i) // len(f)
+        if reps < 1 or (j - i) % len(f) or not np.allclose(np.tile(f[:, :shared], (reps, 1)), F[i:j, :shared]):
+            raise ValueError(f"rows {i}..{j}: seed {seed} {cand_name(cand)} does not match the plan")
+        out[i:j] = np.tile(f, (reps, 1))
+        i = j
+    np.savez_compressed(out_path, features=out, ms=T, seed=S, cand=C)
+    return len(out)
+
+
 # -------------------------------------------------------------------- model
 ADAPTIVE_MARGIN = 0.03
 
@@ -297,6 +333,18 @@ def load_default(device="cuda"):
     return LearnedPlanner.load(DEFAULT_MODEL, device)
 
 
+def combine(paths, out_path):
+    """Concatenate collected timing files into one training set; `source`
+    gives each row's file index."""
+    parts = [np.load(p, allow_pickle=False) for p in paths]
+    cols = {k: np.concatenate([z[k] for z in parts]) for k in ("features", "ms", "seed", "cand")}
+    cols["source"] = np.concatenate([np.full(len(z["ms"]), i, dtype=np.int32) for i, z in enumerate(parts)])
+    if cols["features"].shape[1] != NFEAT:
+        raise ValueError(f"features have {cols['features'].shape[1]} columns, the planner emits {NFEAT}")
+    np.savez_compressed(out_path, **cols)
+    return len(cols["ms"])
+
+
 def load_rows(*paths):
     F, T = [], []
     for p in paths:
@@ -348,13 +396,21 @@ def max_abs_vs_c128(fused, plain, chunk=1 << 26):
     return worst
 
 
+# fixed settings timed beside the learned choice on held-out circuits: every
+# tile setting (the fallback among them) and the classic one block per pass
+EVAL_CANDIDATES = [c for c in CANDIDATES if c[0] == "tile"] + [CLASSIC]
+
+
 def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26, 32),
-             g_range=(100, 500), mix=False, log=True):
-    """Held-out circuits: measured time (best of `reps` runs) of the learned
-    choice and of every fixed candidate setting (the fallback tile-4-13
-    among them), and, with check, the learned plan's whole final state
-    against the plain complex128 path.  mix: circuits from the family
-    mixture instead of the random planner workload."""
+             g_range=(100, 500), mix=False, log=True, cand_reps=2, cands=None, report=None):
+    """Held-out circuits: measured time of the learned choice (best of
+    `reps` runs) and of every fixed setting in `cands` (EVAL_CANDIDATES by
+    default, best of `cand_reps` runs; the fallback tile-4-13 among them),
+    and, with check, the learned plan's whole final state against the plain
+    complex128 path.  mix: circuits from the family mixture instead of the
+    random planner workload.  report: a JSON file rewritten every ten
+    circuits (a cut-short run keeps what it measured)."""
+    cands = EVAL_CANDIDATES if cands is None else cands
     import torch
     from workloads import planner_mix_circuit
     if mix:
@@ -375,16 +431,16 @@ def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26
         tp = time.perf_counter()
         cand, plan, pred = planner.choose(ga, n, dtype)
         plan_ms = (time.perf_counter() - tp) * 1e3
-        best = lambda p: min(time_plan(sv, p)[0] for _ in range(reps))
+        best = lambda p, r: min(time_plan(sv, p)[0] for _ in range(r))
         rec = {"seed": s, "n": n, "gates": len(gates), "choice": cand_name(cand), "pred_ms": pred,
-               "plan_ms": plan_ms, "learned_ms": best(plan)}
+               "plan_ms": plan_ms, "learned_ms": best(plan, reps)}
         if plan.k_of_pass is not None:
-            rec["k_of_pass"] = plan.k_of_pass
+            rec["k_of_pass"] = [int(k) for k in plan.k_of_pass]
         allm = {}
-        for c in CANDIDATES:
+        for c in cands:
             p = build_plan(ga, n, dtype, c)
             if p is not None:
-                allm[cand_name(c)] = best(p)
+                allm[cand_name(c)] = best(p, cand_reps)
         rec["all_ms"] = allm
         if check:
             # the learned plan's whole state against the unfused complex128 path
@@ -397,8 +453,12 @@ def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26
             del plain
             torch.cuda.empty_cache()
         recs.append(rec)
-        if log and ((i + 1) % 10 == 0 or i + 1 == len(jobs)):
-            print(f"evaluate: {i + 1}/{len(jobs)} circuits, {time.time() - t0:.0f} s", flush=True)
+        if (i + 1) % 10 == 0 or i + 1 == len(jobs):
+            if report:
+                with open(report, "w") as fh:
+                    json.dump({"records": recs}, fh)
+            if log:
+                print(f"evaluate: {i + 1}/{len(jobs)} circuits, {time.time() - t0:.0f} s", flush=True)
     return recs
 
 
@@ -462,7 +522,7 @@ def explain(planner, n, gates, x=0, dtype="c64", measure=True):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["collect", "train", "evaluate", "explain", "summarize"])
+    ap.add_argument("cmd", choices=["collect", "refeature", "combine", "train", "evaluate", "explain", "summarize"])
     ap.add_argument("--workload", default="qft30", help="explain: a named workload of workloads.config_circuit")
     ap.add_argument("--first", type=int, default=0)
     ap.add_argument("--count", type=int, default=2000)
@@ -479,6 +539,11 @@ def main():
     if a.cmd == "collect":
         rows = collect(a.first, a.count, a.out, mix=not a.no_mix)
         print(f"collected {rows} pass timings", flush=True)
+    elif a.cmd == "refeature":
+        rows = refeature(a.data[0], a.out, mix=not a.no_mix)
+        print(f"recomputed features of {rows} pass timings", flush=True)
+    elif a.cmd == "combine":
+        print(f"combined {combine(a.data, a.out)} pass timings", flush=True)
     elif a.cmd == "train":
         F, T = load_rows(*a.data)
         planner, hist = train(F, T, epochs=a.epochs)
@@ -493,9 +558,7 @@ def main():
             print(json.dumps(r), flush=True)
     elif a.cmd == "evaluate":
         planner = LearnedPlanner.load(a.model)
-        recs = evaluate(planner, a.first, a.count, mix=a.mix, check=not a.no_check)
-        with open(a.report, "w") as fh:
-            json.dump({"records": recs}, fh)
+        recs = evaluate(planner, a.first, a.count, mix=a.mix, check=not a.no_check, report=a.report)
         print(json.dumps(summarize(recs)), flush=True)
     elif a.cmd == "summarize":
         recs = []
