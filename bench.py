@@ -248,8 +248,8 @@ def layered_configs(torch, planner, records):
                     setting = "%s, k_max %d, tile %d" % tuple(cand)
                 else:
                     tile = min(n, 13 if dtype == "c64" else 12)
-                    plan = qvm.Plan(ga, n, dtype, k_max=4, tile_qubits=tile)
-                    setting = f"tile, k_max 4, tile {tile}"
+                    plan = qvm.Plan(ga, n, dtype, k_max=3, tile_qubits=tile)
+                    setting = f"tile, k_max 3, tile {tile}"
                 runner = lambda: plan.run(sv)
                 st = plan.stats()
                 extra = {"setting": setting, "passes": st["passes"], "blocks": st["blocks"]}
@@ -389,7 +389,7 @@ def main():
     ap.add_argument("--planner", choices=["learned", "fixed"], default="learned",
                     help="learned: the cost-model MLP picks among candidate plans (falls back to "
                          "'fixed' when no trained model is present); fixed: --k-max/--tile")
-    ap.add_argument("--k-max", type=int, default=4)
+    ap.add_argument("--k-max", type=int, default=3)
     ap.add_argument("--tile", type=int, default=13, help="tile qubits per pass (0: one block per pass)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--no-noise", action="store_true", help="skip the Kraus-trajectory workload")
@@ -564,7 +564,7 @@ def main():
                           "TFLOPs": v["flops"] / (v["total_ms"] / 1e3) / 1e12 if v["total_ms"] else None}
                       for k, v in kstats.items()}
     # outside the timed steps: the greedy planner without the model, at the
-    # setting it falls back to (4-qubit blocks in 13-qubit tiles) and at the
+    # setting it falls back to (3-qubit blocks in 13-qubit tiles) and at the
     # classic fused-gate setting (one 5-qubit block per pass), beside the
     # learned choice
     if planner is not None:

@@ -47,7 +47,7 @@ DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
               ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13),
               ("tile", 3, 12), ("tile", 4, 12), ("tile", 5, 12), ("tile", 3, 11)]
-FALLBACK = ("tile", 4, 13)     # the greedy planner's setting when no model is shipped
+FALLBACK = ("tile", 3, 13)     # the greedy planner's setting when no model is shipped
 CLASSIC = ("block", 5, 0)      # the classic fused-gate simulator: 5-qubit blocks, one pass each
 # tile widths at which the model also picks the block width of every pass
 ADAPTIVE_TILES = (13, 12)
@@ -405,7 +405,7 @@ def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26
              g_range=(100, 500), mix=False, log=True, cand_reps=2, cands=None, report=None):
     """Held-out circuits: measured time of the learned choice (best of
     `reps` runs) and of every fixed setting in `cands` (EVAL_CANDIDATES by
-    default, best of `cand_reps` runs; the fallback tile-4-13 among them),
+    default, best of `cand_reps` runs; the fallback tile-3-13 among them),
     and, with check, the learned plan's whole final state against the plain
     complex128 path.  mix: circuits from the family mixture instead of the
     random planner workload.  report: a JSON file rewritten every ten

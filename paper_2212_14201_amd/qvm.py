@@ -182,7 +182,7 @@ class Circuit:
 
 
 def plan(circuit, n: int | None = None, dtype: str = "c64", planner: str = "greedy",
-         k_max: int = 4, tile_qubits: int = 13) -> "Plan":
+         k_max: int = 3, tile_qubits: int = 13) -> "Plan":
     """A fused plan for a Circuit (or gate list).  planner="greedy": the
     greedy planner at (k_max, tile_qubits); planner="learned": the shipped
     cost model's choice among the candidate settings (needs the GPU for the

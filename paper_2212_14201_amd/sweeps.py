@@ -125,8 +125,8 @@ def sweep_circuit(ns, layers=10, seed=11):
                 cand, plan, _ = planner.choose(ga, n, "c64")
                 rec["planner"] = "learned: %s, k_max %d, tile %d" % cand
             else:
-                plan = qvm.Plan(ga, n, "c64", k_max=4, tile_qubits=13)
-                rec["planner"] = "greedy: k_max 4, tile 13"
+                plan = qvm.Plan(ga, n, "c64", k_max=3, tile_qubits=13)
+                rec["planner"] = "greedy: k_max 3, tile 13"
             t1 = time.perf_counter()
             plan.run(fused)
             torch.cuda.synchronize()
@@ -142,7 +142,7 @@ def sweep_circuit(ns, layers=10, seed=11):
 
 def sweep_simplify(first=100_000, count=20, n_range=(26, 28)):
     """The peephole pre-pass on planner-workload circuits: gate counts and the
-    fused complex64 run time (greedy, 4-qubit blocks in 13-qubit tiles)
+    fused complex64 run time (greedy, 3-qubit blocks in 13-qubit tiles)
     without and with it."""
     import torch
     from . import qvm
@@ -160,7 +160,7 @@ def sweep_simplify(first=100_000, count=20, n_range=(26, 28)):
             sv = qvm.StateVector(n, "c64", init=0)
         rec = {"sweep": "simplify", "seed": s, "n": n, "gates": ga.n, "kept": sa.n, "simplify_ms": ts}
         for tag, arr in (("original", ga), ("simplified", sa)):
-            plan = qvm.Plan(arr, n, "c64", k_max=4, tile_qubits=13)
+            plan = qvm.Plan(arr, n, "c64", k_max=3, tile_qubits=13)
             sv.init_basis(0)
             plan.run(sv)
             sv.init_basis(0)

@@ -129,12 +129,12 @@ def test_layered_28_qubits(path, request):
 
 def bench_plan(gates, n):
     """The plan bench.py times: the shipped learned planner's choice, or the
-    greedy planner with 4-qubit blocks in 13-qubit tiles without a model."""
+    greedy planner with 3-qubit blocks in 13-qubit tiles without a model."""
     from paper_2212_14201_amd import learned_planner
     planner = learned_planner.load_default()
     ga = qvm.GateArray(gates)
     if planner is None:
-        return qvm.Plan(ga, n, "c64", k_max=4, tile_qubits=13)
+        return qvm.Plan(ga, n, "c64", k_max=3, tile_qubits=13)
     return planner.choose(ga, n, "c64")[1]
 
 

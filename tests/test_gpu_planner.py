@@ -55,7 +55,7 @@ def plan_tau(plan):
 def test_trained_model_against_the_fallback():
     """The shipped model on held-out circuits of the planner workload (26-28
     qubits, 100-500 gates) against the greedy planner without it (its
-    fallback setting, 4-qubit blocks in 13-qubit tiles): the measured total
+    fallback setting, 3-qubit blocks in 13-qubit tiles): the measured total
     of the learned choices must not exceed the fallback's by more than 2%
     (the gain is printed), and the learned plan's whole state must agree
     with the plain complex128 path within 1e-5."""
