@@ -515,9 +515,8 @@ __device__ __forceinline__ void fetch_frag(R (&dst)[NF], const TOp& b, const cha
 // except before blocks marked BLK_NOSYNC.
 template <typename R, int L, int NF>
 __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp* __restrict__ ops, const PassDesc& pd,
-                                                 const char* __restrict__ blob, uint64_t base) {
-    R fa[NF], fb[NF];
-    if (pd.first_block >= 0) fetch_frag<R, NF>(fa, ops[pd.first_block], blob);
+                                                 const char* __restrict__ blob, uint64_t base, R (&fa)[NF]) {
+    R fb[NF];
     bool first = true;           // the barrier after the load phase covers the first op
     for (int oi = 0; oi < pd.nops; ++oi) {
         const TOp& op = ops[oi];
@@ -558,19 +557,26 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
 // The tile is read and written once per pass with nontemporal accesses (the
 // state streams through; caching it in L2 gains nothing).
 //
+// Stream phases: thread t moves the 16-byte pieces t + NT i (i < NIT) of the
+// tile, tile element e = EP (t + NT i).  Its chunk of 2^C elements is
+// e >> C = (EP t >> C) + (EP NT >> C) i and its offset in the chunk EP t mod
+// 2^C (EP NT is a multiple of 2^C); the chunk-offset and remap tables are
+// linear over disjoint bits (deposits and bit permutations), so a piece's
+// entry is the thread's entry OR the uniform entry of i: one per-thread
+// table load per phase, the rest scalar loads.
+//
 // Passes whose blocks are all of 3 or 4 qubits keep every block's A
-// fragments in registers (fetched one block ahead) and need no LDS fragment
-// area; a workgroup barrier separates consecutive ops except blocks marked
+// fragments in registers (the first block's fetched before the load phase,
+// each later block's one block ahead) and need no LDS fragment area; a
+// workgroup barrier separates consecutive ops except blocks marked
 // BLK_NOSYNC, whose waves touch the same elements as in the block before.
 // Passes with wider blocks stage each block's fragments in LDS, with a
 // barrier after every op.
-template <typename R, int L>
-__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
-                                                 const char* __restrict__ blob) {
+template <typename R, int L, int MODE>   // MODE: 4 or 16 fragment registers, 0 LDS fragments
+__device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& pd, const char* __restrict__ blob) {
     extern __shared__ __align__(16) char smem[];
     // LDS: the tile first (at address 0, so tile addresses need no base),
-    // the widest block's fragments after it (their reads take constant
-    // offsets from a per-lane base)
+    // in passes with wider blocks the widest block's fragments after it
     R* lds = (R*)smem;
     R* ldsA = lds + (2u << L);
     constexpr int EP = TT<R>::EP;
@@ -579,40 +585,41 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     constexpr int NIT = NP >= NT ? (int)(NP / NT) : 1;       // pieces per thread
     constexpr int BATCH = NIT < 4 ? NIT : 4;
     constexpr uint32_t CM = (1u << C) - 1;
+    constexpr uint32_t HI = (uint32_t)EP * NT >> C;          // chunk step of piece i
+    static_assert(((uint32_t)EP * NT & CM) == 0, "pieces i > 0 start on chunk boundaries");
     using V16 = typename TT<R>::V16;
     const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
     const uint64_t* __restrict__ ldoff = (const uint64_t*)(blob + pd.ldoff);
+    const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
     const bool live = threadIdx.x < NP;
+    const uint32_t e0 = EP * threadIdx.x;
+    R fa[MODE > 0 ? MODE : 1];
+    if constexpr (MODE > 0)
+        if (pd.first_block >= 0) fetch_frag<R, MODE>(fa, ops[pd.first_block], blob);
+    // the thread's piece offsets: its table entry plus the uniform one of i
+    uint64_t tofs = 0;
+    if (live) tofs = base + ldoff[e0 >> C] + (e0 & CM);
 
-    // load: per batch, all addresses first, then all loads in flight, then LDS
+    // load: per batch, all loads in flight, then LDS
     if (live) {
 #pragma unroll
         for (int b0 = 0; b0 < NIT; b0 += BATCH) {
-            uint64_t g[BATCH];
             V16 v[BATCH];
 #pragma unroll
-            for (int it = 0; it < BATCH; ++it) {
-                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
-                g[it] = base + ldoff[e >> C] + (e & CM);
-            }
-#pragma unroll
-            for (int it = 0; it < BATCH; ++it) v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * g[it]));
+            for (int it = 0; it < BATCH; ++it)
+                v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * (tofs + ldoff[HI * (b0 + it)])));
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
-                const uint32_t e = (threadIdx.x + NT * (uint32_t)(b0 + it)) * EP;
+                const uint32_t e = e0 + (uint32_t)EP * NT * (uint32_t)(b0 + it);
                 *(V16*)(lds + 2 * sw(e)) = v[it];
             }
         }
     }
     __syncthreads();
 
-    const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
-    if (pd.kmax <= 3) {
-        tile_ops_regfrag<R, L, 4>(lds, ops, pd, blob, base);
-    } else if (pd.kmax == 4) {
-        tile_ops_regfrag<R, L, 16>(lds, ops, pd, blob, base);
+    if constexpr (MODE > 0) {
+        tile_ops_regfrag<R, L, MODE>(lds, ops, pd, blob, base, fa);
     } else {
-    R fa[1];                     // unused: wider passes read fragments from LDS
     // fragments: the first block's are copied to LDS with the tile (the
     // barrier below covers them); each later block's are read into
     // registers while the block before it runs and stored to LDS after it.
@@ -686,39 +693,40 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
     }
 
     // store: per batch, LDS reads first (optionally through the tile-bit
-    // remap), then the global stores.  The slots and chunk offsets are
-    // computed again rather than kept in registers from the load phase
-    // through every op (the opaque copy of the thread index stops the reuse).
-    uint32_t tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
+    // remap), then the global stores.  Passes with more fragment registers
+    // read the thread's chunk offset again rather than keep it through the
+    // ops (the opaque copy of the thread index stops the reuse).
+    if constexpr (MODE != 4) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (live) tofs = base + ldoff[(EP * tid) >> C] + ((EP * tid) & CM);
+    }
     if (live) {
         const uint32_t* __restrict__ rmhi = (const uint32_t*)(blob + pd.rmhi);
         const uint32_t* __restrict__ rmlo = (const uint32_t*)(blob + pd.rmlo);
         const bool remap = pd.remap != 0;
+        uint32_t rh0 = 0, rl0 = 0, rl1 = 0;     // the thread's remap entries
+        if (remap) {
+            rh0 = rmhi[e0 >> C];
+            rl0 = rmlo[e0 & CM];
+            rl1 = EP == 2 ? rmlo[(e0 + 1) & CM] : 0u;
+        }
 #pragma unroll
         for (int b0 = 0; b0 < NIT; b0 += BATCH) {
             V16 v[BATCH];
             if (!remap) {
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t d = (tid + NT * (uint32_t)(b0 + it)) * EP;
+                    const uint32_t d = e0 + (uint32_t)EP * NT * (uint32_t)(b0 + it);
                     v[it] = *(const V16*)(lds + 2 * sw(d));
                 }
             } else {
-                // table reads first (all in flight), then the LDS gathers
-                uint32_t hi[BATCH], lo0[BATCH], lo1[BATCH];
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t d = (tid + NT * (uint32_t)(b0 + it)) * EP;
-                    hi[it] = rmhi[d >> C];
-                    lo0[it] = rmlo[d & CM];
-                    lo1[it] = EP == 2 ? rmlo[(d + 1) & CM] : 0u;
-                }
-#pragma unroll
-                for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t s0 = 2 * sw(hi[it] | lo0[it]);
+                    const uint32_t hi = rh0 | rmhi[HI * (b0 + it)];
+                    const uint32_t s0 = 2 * sw(hi | rl0);
                     if constexpr (EP == 2) {
-                        const uint32_t s1 = 2 * sw(hi[it] | lo1[it]);
+                        const uint32_t s1 = 2 * sw(hi | rl1);
                         v[it] = V16{lds[s0], lds[s0 + 1], lds[s1], lds[s1 + 1]};
                     } else {
                         v[it] = V16{lds[s0], lds[s0 + 1]};
@@ -726,12 +734,17 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restri
                 }
             }
 #pragma unroll
-            for (int it = 0; it < BATCH; ++it) {
-                const uint32_t e = (tid + NT * (uint32_t)(b0 + it)) * EP;
-                __builtin_nontemporal_store(v[it], (V16*)(psi + 2 * (base + ldoff[e >> C] + (e & CM))));
-            }
+            for (int it = 0; it < BATCH; ++it)
+                __builtin_nontemporal_store(v[it], (V16*)(psi + 2 * (tofs + ldoff[HI * (b0 + it)])));
         }
     }
+}
+
+// One kernel per fragment mode, so that each gets its own register budget.
+template <typename R, int L, int MODE>
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
+                                                 const char* __restrict__ blob) {
+    tile_pass<R, L, MODE>(psi, pd, blob);
 }
 
 size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
@@ -744,15 +757,19 @@ size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
 template <typename R>
 static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, size_t lds,
                                 double flops) {
-    static bool attr_set[64][16] = {};       // per device and tile size
+    static bool attr_set[64][16][3] = {};    // per device, tile size and fragment mode
     int dev = 0;
     QVM_HIP(sv, hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(QVM_EUNSUPPORTED, "device index above 63");
     const unsigned grid = 1u << (sv->n - pd.L);
+    const int mode = pd.kmax <= 3 ? 0 : pd.kmax == 4 ? 1 : 2;
     const void* fn = nullptr;
     switch (pd.L) {
-#define QVM_TILE_CASE(LL) \
-        case LL: fn = (const void*)k_tile<R, LL>; break;
+#define QVM_TILE_CASE(LL)                                                          \
+        case LL:                                                                   \
+            fn = mode == 0 ? (const void*)k_tile<R, LL, 4>                         \
+               : mode == 1 ? (const void*)k_tile<R, LL, 16> : (const void*)k_tile<R, LL, 0>; \
+            break;
         QVM_TILE_CASE(3) QVM_TILE_CASE(4) QVM_TILE_CASE(5) QVM_TILE_CASE(6) QVM_TILE_CASE(7)
         QVM_TILE_CASE(8) QVM_TILE_CASE(9) QVM_TILE_CASE(10) QVM_TILE_CASE(11) QVM_TILE_CASE(12)
         QVM_TILE_CASE(13)
@@ -760,9 +777,9 @@ static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob
         default: return fail(QVM_EUNSUPPORTED, "tile size outside 3..13");
     }
     if (pd.c != (TT<R>::C < pd.L ? TT<R>::C : pd.L)) return fail(QVM_EARG, "internal: pass low-bit count");
-    if (!attr_set[dev][pd.L]) {
+    if (!attr_set[dev][pd.L][mode]) {
         QVM_HIP(sv, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLdsMax));
-        attr_set[dev][pd.L] = true;
+        attr_set[dev][pd.L][mode] = true;
     }
     R* amps = (R*)sv->amps;
     void* args[] = {(void*)&amps, (void*)&pd, (void*)&blob_dev};
