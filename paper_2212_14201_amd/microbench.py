@@ -111,7 +111,7 @@ def main():
     else:
         cfg = config_circuit("qft30") if a.n == 30 else None
         gates = cfg["gates"] if cfg else [Gate("h", (q,)) for q in range(a.n)]
-        plan = qvm.Plan(gates, a.n, a.dtype, k_max=4, tile_qubits=13 if a.dtype == "c64" else 12)
+        plan = qvm.Plan(gates, a.n, a.dtype, k_max=3, tile_qubits=13 if a.dtype == "c64" else 12)
         for _ in range(a.launches):
             sv.init_basis(0)
             plan.run(sv)
