@@ -10,6 +10,7 @@ counters for a plain device copy of known size (the scale factor).
     python -m paper_2212_14201_amd.microbench --kernel stream --n 30 --launches 5
     python -m paper_2212_14201_amd.microbench --kernel blocks --k 4 --blocks 32 --n 30 --launches 2
     python -m paper_2212_14201_amd.microbench --kernel phase --qubits 0 1 --n 30 --dtype c128
+    python -m paper_2212_14201_amd.microbench --kernel adjoint --launches 3
 """
 import argparse
 import os
@@ -20,7 +21,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--kernel", choices=["dense1", "phase", "tile", "copy", "stream", "blocks"], required=True)
+    ap.add_argument("--kernel", choices=["dense1", "phase", "tile", "copy", "stream", "blocks", "adjoint"],
+                    required=True)
     ap.add_argument("--qubits", type=int, nargs=2, default=(0, 1), help="phase: the CZ's control and target")
     ap.add_argument("--k", type=int, default=4, help="blocks: block width in qubits")
     ap.add_argument("--blocks", type=int, default=32, help="blocks: fused blocks in the one tile pass")
@@ -69,6 +71,22 @@ def main():
             plan.run(sv)
         ms = timed(run, a.launches) - timed(lambda: sv.init_basis(0), a.launches)
         print(f"tile pass complex64 (one CZ): {ms:.3f} ms, {2 * 8 * 2**a.n / ms / 1e6:.0f} GB/s", flush=True)
+        return
+    if a.kernel == "adjoint":
+        # the batched adjoint workload: 20 qubits, complex64, 16 layers of
+        # RY, RZ and a CNOT ladder (944 gates), 40 Pauli terms, batch 64
+        import math
+        import numpy as np
+        from paper_2212_14201_amd import adjoint
+        from workloads import SEEDS, hardware_efficient_ansatz, random_pauli_sum
+        gates, P = hardware_efficient_ansatz(20, 16)
+        xs, zs, cs, _ = random_pauli_sum(20, 40, SEEDS["pauli20"])
+        theta = np.random.Generator(np.random.PCG64(SEEDS["hea20"])).uniform(0, 2 * math.pi, (64, P))
+        prob = adjoint.AdjointProblem(20, gates, P, xs, zs, cs, 64, "c64")
+        for _ in range(a.launches):
+            prob.run(theta)
+        torch.cuda.synchronize()
+        print(f"adjoint batch 64 x {a.launches}", flush=True)
         return
     if a.kernel == "blocks":
         # one complex64 tile pass (tiles of `tile` qubits) holding `blocks` random
