@@ -386,6 +386,50 @@ void angle_terms(const std::vector<DSub>& run, int L, qvm_dtype dt, const int8_t
     }
 }
 
+// Bits of x at the zero positions of qmask (the tile's outer bits), packed
+// in ascending order: x's bits as bits of the tile (workgroup) index.
+static uint32_t outer_bits(uint64_t x, uint64_t qmask) {
+    uint32_t r = 0;
+    int j = 0;
+    for (int p = 0; p < 64 && j < 32; ++p) {
+        if ((qmask >> p) & 1) continue;
+        if ((x >> p) & 1) r |= 1u << j;
+        ++j;
+    }
+    return r;
+}
+
+// Epilogue-run records (ETerm) from the grouped angle-path terms of a run
+// over the epilogue layout (four element-code bits): outer conditions over
+// the tile index, sign runs with their groups' element-code sets, every
+// group padded to an even count.
+void epilogue_terms(const std::vector<DTerm>& terms, const std::vector<uint32_t>& off, uint64_t qmask, bool signs,
+                    std::vector<ETerm>& et, std::vector<uint32_t>& eoff) {
+    et.clear();
+    eoff.assign(17, 0);
+    for (uint32_t g = 0; g < 16; ++g) {
+        uint32_t sup = 0;                                  // element codes containing g
+        for (uint32_t i = 0; i < 16; ++i)
+            if ((i & g) == g) sup |= 1u << i;
+        for (uint32_t q = off[g]; q < off[g + 1]; ++q) {
+            const DTerm& d = terms[q];
+            ETerm e{};
+            e.om = outer_bits(d.omask, qmask);
+            e.ov = outer_bits(d.oval, qmask);
+            e.lm = d.lmask;
+            e.lv = d.lval;
+            e.w = signs ? sup : (uint32_t)d.turns;
+            et.push_back(e);
+        }
+        if (et.size() & 1) {
+            ETerm pad{};
+            pad.ov = 1;                                    // (w & 0) != 1: never matches
+            et.push_back(pad);
+        }
+        eoff[g + 1] = (uint32_t)et.size();
+    }
+}
+
 // The standalone run's element layout: thread t holds elements
 // t + kTileThreads i, so tile bits below kLogTileThreads are thread bits and
 // the ones above are element bits.
@@ -958,9 +1002,12 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             std::vector<DTerm> terms;
             std::vector<uint32_t> off;
             angle_terms(er.second, L, dt, bitmap, 4, terms, off);
+            std::vector<ETerm> et;
+            std::vector<uint32_t> eoff;
+            epilogue_terms(terms, off, qmask, (o.flags & DRUN_SIGNS) != 0, et, eoff);
             o.k = (int32_t)terms.size();
-            o.data = B.put(terms.data(), terms.size() * sizeof(DTerm));
-            o.tab = B.put(off.data(), off.size() * sizeof(uint32_t));
+            o.data = B.put(et.data(), et.size() * sizeof(ETerm));
+            o.tab = B.put(eoff.data(), eoff.size() * sizeof(uint32_t));
         }
         if (image)
             for (size_t oi = 0; oi < ops.size(); ++oi) {

@@ -65,22 +65,16 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 
 __device__ __forceinline__ uint32_t sw(uint32_t e) { return tile_swizzle(e); }
 
-__device__ __forceinline__ uint32_t dep32(uint32_t w, uint32_t fixed) {
-    while (fixed) {
-        uint32_t low = fixed & (~fixed + 1);
-        uint32_t lo = w & (low - 1);
-        w = ((w - lo) << 1) | lo;
-        fixed ^= low;
-    }
-    return w;
-}
-
+// w with a zero inserted at every set bit of `fixed` (the tile bits), one
+// run of consecutive set bits at a time: the tile's base index from its
+// workgroup index.
 __device__ __forceinline__ uint64_t dep64(uint64_t w, uint64_t fixed) {
     while (fixed) {
-        uint64_t low = fixed & (~fixed + 1);
-        uint64_t lo = w & (low - 1);
-        w = ((w - lo) << 1) | lo;
-        fixed ^= low;
+        const uint64_t low = fixed & (~fixed + 1);
+        const uint64_t run = ((fixed + low) & ~fixed) - low;     // the lowest run of ones
+        const uint64_t lo = w & (low - 1);
+        w = ((w - lo) << __builtin_popcountll(run)) | lo;
+        fixed &= ~run;
     }
     return w;
 }
@@ -196,6 +190,55 @@ __device__ __forceinline__ void sload(uint32_t (&dst)[N], const uint32_t* __rest
     }
 }
 
+// Runs applied in a block's epilogue (ETerm records, complex64): whether a
+// record matches thread t of tile w, as a vector test (tile-index test and
+// thread test in one compare, no scalar compares); two records per scalar
+// load (groups are padded to even counts).
+__device__ __forceinline__ bool eterm_on(const uint32_t* r, uint32_t w, uint32_t t) {
+    return (((w & r[0]) ^ r[1]) | ((t ^ r[3]) & r[2])) == 0;
+}
+
+// A sign run: bit i of the result is the parity of the thread's matching
+// terms whose group is contained in element code i (each record holds the
+// codes its group is contained in), i.e. whether element i changes sign.
+__device__ __forceinline__ uint32_t erun_signs(const ETerm* __restrict__ terms, const uint32_t* __restrict__ grp,
+                                               uint32_t w, uint32_t t) {
+    const uint32_t n = grp[16];
+    uint32_t m = 0;
+#pragma unroll 1
+    for (uint32_t q = 0; q < n; q += 2) {
+        uint32_t r[16];
+        sload<16>(r, (const uint32_t*)(terms + q));
+        m ^= eterm_on(r, w, t) ? r[4] : 0u;
+        m ^= eterm_on(r + 8, w, t) ? r[12] : 0u;
+    }
+    return m;
+}
+
+// A phase run: the thread's angle per element code (turns of 2^-32), one
+// sum per group, then subset sums over the four element-code bits.
+__device__ __forceinline__ void erun_angles(uint32_t (&acc)[16], const ETerm* __restrict__ terms,
+                                            const uint32_t* __restrict__ grp, uint32_t w, uint32_t t) {
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+        uint32_t a = 0;
+        const uint32_t q1 = grp[g + 1];
+#pragma unroll 1
+        for (uint32_t q = grp[g]; q < q1; q += 2) {
+            uint32_t r[16];
+            sload<16>(r, (const uint32_t*)(terms + q));
+            a += eterm_on(r, w, t) ? r[4] : 0u;
+            a += eterm_on(r + 8, w, t) ? r[12] : 0u;
+        }
+        acc[g] = a;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((i >> b) & 1) acc[i] += acc[i ^ (1 << b)];
+}
+
 // ---------------------------------------------------------------- blocks
 // The block's real fragments are already in LDS (after the tile; the
 // kernel stages them while the previous op runs); every k-step reads one A
@@ -217,7 +260,9 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 //
 // With RUN (complex64, 13-qubit tiles, 3- and 4-qubit blocks: one column
 // iteration per wave) the diagonal run that follows the block is applied to
-// the outputs before they are stored.  The run's terms are encoded over the
+// the outputs before they are stored: RUN = 1 a run of phases (one factor
+// per element from its angle sum), RUN = 2 a run of sign flips (one parity
+// bit per element).  The run's terms are encoded over the
 // epilogue's layout: thread code threadIdx.x (lane l holds column bits 0..3
 // as l % 16 and block bits 1, 2 as l / 16; the wave holds the top column
 // bits) and element code hh | ct << 1 | rb << (1 + log2 CT) (block bit 0,
@@ -226,11 +271,11 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // With GA (blocks of up to 4 qubits in passes without wider blocks) the A
 // fragments come from the caller's registers (fetched from the plan one
 // block ahead) instead of the LDS fragment area.
-template <typename R, int K, int LT, bool RUN = false, bool GA = false, int NF = 1>
+template <typename R, int K, int LT, int RUN = 0, bool GA = false, int NF = 1>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NF],
                                            const TOp& op, const char* __restrict__ blob, int L_,
-                                           const TOp* __restrict__ run = nullptr, uint64_t base = 0) {
-    static_assert(!RUN || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
+                                           const TOp* __restrict__ run = nullptr) {
+    static_assert(RUN == 0 || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
     constexpr int L = LT;                      // the kernel's tile width
     (void)L_;
@@ -342,16 +387,20 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
             }
         }
         using TU = typename Turn<R>::T;
-        constexpr int NEC = RUN ? 16 : 1;
+        constexpr int NEC = RUN == 1 ? 16 : 1;
         constexpr int LCT = CT == 8 ? 3 : CT == 4 ? 2 : CT == 2 ? 1 : 0;
         TU ang[NEC];
-        bool signs = false;
-        if constexpr (RUN) {
-            static_assert(2 * CT * RB == NEC, "epilogue element code");
-            run_angles<TU, 4>(ang, (const DTerm*)(blob + run->data), (const uint32_t*)(blob + run->tab), base,
-                              threadIdx.x);
-            signs = (run->flags & DRUN_SIGNS) != 0;
-        }
+        static_assert(RUN == 0 || 2 * CT * RB == 16, "epilogue element code");
+        // the tile index: a vector operand where registers allow (the run's
+        // tile-index tests then take no scalar instructions)
+        uint32_t wv = blockIdx.x;
+        if constexpr (RUN != 0 && GA && NF == 4) asm volatile("" : "+v"(wv));
+        if constexpr (RUN == 1)
+            erun_angles(ang, (const ETerm*)(blob + run->data), (const uint32_t*)(blob + run->tab), wv, threadIdx.x);
+        // a sign run: the thread's flips, one bit per element code
+        uint32_t smask = 0;
+        if constexpr (RUN == 2)
+            smask = erun_signs((const ETerm*)(blob + run->data), (const uint32_t*)(blob + run->tab), wv, threadIdx.x);
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             if (!ok[ct]) continue;
@@ -364,18 +413,17 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                     for (int hh = 0; hh < 2; ++hh) {
                         const uint32_t sl = pout ^ __builtin_amdgcn_readfirstlane(cw[ct] ^ ew[4 * rb + hh]);
                         R yr = acc[ct][rb][2 * hh], yi = acc[ct][rb][2 * hh + 1];
-                        if constexpr (RUN) {
-                            const TU a = ang[(hh | ct << 1 | rb << (1 + LCT)) % NEC];
-                            if (signs) {
-                                yr = flip_if(yr, a);
-                                yi = flip_if(yi, a);
-                            } else {
-                                R fr, fi;
-                                cis_turns(a, fr, fi);
-                                const R xr = yr;
-                                yr = fr * xr - fi * yi;
-                                yi = fr * yi + fi * xr;
-                            }
+                        const int ec = hh | ct << 1 | rb << (1 + LCT);   // element code
+                        if constexpr (RUN == 2) {
+                            const uint32_t f = (smask << (31 - ec)) & 0x80000000u;
+                            yr = __uint_as_float(__float_as_uint(yr) ^ f);
+                            yi = __uint_as_float(__float_as_uint(yi) ^ f);
+                        } else if constexpr (RUN == 1) {
+                            R fr, fi;
+                            cis_turns(ang[ec % NEC], fr, fi);
+                            const R xr = yr;
+                            yr = fr * xr - fi * yi;
+                            yi = fr * yi + fi * xr;
                         }
                         lds_st<typename TT<R>::V2>(sl, typename TT<R>::V2{yr, yi});
                     }
@@ -531,13 +579,17 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
             if (nb >= 0) fetch_frag<R, NF>(fb, ops[nb], blob);
             // a diagonal run right after the block may ride in its epilogue
             constexpr bool RUNOK = sizeof(R) == 4 && L == 13;
-            const bool erun = RUNOK && (op.flags & BLK_RUN) != 0;
+            constexpr int RP = RUNOK ? 1 : 0, RS = RUNOK ? 2 : 0;
+            const int erun = !RUNOK || !(op.flags & BLK_RUN) ? 0 : (ops[oi + 1].flags & DRUN_SIGNS) ? 2 : 1;
+            const TOp* run = &ops[oi + 1];
             if (NF == 4 || op.k == 3) {
-                if (erun) tile_block<R, 16, L, RUNOK, true>(lds, lds, fa, op, blob, L, &ops[oi + 1], base);
-                else tile_block<R, 16, L, false, true>(lds, lds, fa, op, blob, L);
+                if (erun == 2) tile_block<R, 16, L, RS, true>(lds, lds, fa, op, blob, L, run);
+                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, op, blob, L, run);
+                else tile_block<R, 16, L, 0, true>(lds, lds, fa, op, blob, L);
             } else if constexpr (NF >= 16) {
-                if (erun) tile_block<R, 32, L, RUNOK, true>(lds, lds, fa, op, blob, L, &ops[oi + 1], base);
-                else tile_block<R, 32, L, false, true>(lds, lds, fa, op, blob, L);
+                if (erun == 2) tile_block<R, 32, L, RS, true>(lds, lds, fa, op, blob, L, run);
+                else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, op, blob, L, run);
+                else tile_block<R, 32, L, 0, true>(lds, lds, fa, op, blob, L);
             }
             if (nb >= 0) {
 #pragma unroll
@@ -588,17 +640,32 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     constexpr uint32_t HI = (uint32_t)EP * NT >> C;          // chunk step of piece i
     static_assert(((uint32_t)EP * NT & CM) == 0, "pieces i > 0 start on chunk boundaries");
     using V16 = typename TT<R>::V16;
-    const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
     const uint64_t* __restrict__ ldoff = (const uint64_t*)(blob + pd.ldoff);
+    const uint32_t* __restrict__ rmhi = (const uint32_t*)(blob + pd.rmhi);
+    const uint32_t* __restrict__ rmlo = (const uint32_t*)(blob + pd.rmlo);
     const TOp* __restrict__ ops = (const TOp*)(blob + pd.ops);
     const bool live = threadIdx.x < NP;
+    const bool remap = pd.remap != 0;
     const uint32_t e0 = EP * threadIdx.x;
+    // the thread's table entries first (the tile loads wait for them only):
+    // its chunk offset and, in passes with few fragment registers, its remap
+    // entries for the store phase
+    uint64_t tofs = 0;
+    uint32_t rh0 = 0, rl0 = 0, rl1 = 0;
+    if (live) {
+        tofs = ldoff[e0 >> C] + (e0 & CM);
+        if (MODE == 4 && remap) {
+            rh0 = rmhi[e0 >> C];
+            rl0 = rmlo[e0 & CM];
+            rl1 = EP == 2 ? rmlo[(e0 + 1) & CM] : 0u;
+        }
+    }
     R fa[MODE > 0 ? MODE : 1];
     if constexpr (MODE > 0)
         if (pd.first_block >= 0) fetch_frag<R, MODE>(fa, ops[pd.first_block], blob);
+    const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
     // the thread's piece offsets: its table entry plus the uniform one of i
-    uint64_t tofs = 0;
-    if (live) tofs = base + ldoff[e0 >> C] + (e0 & CM);
+    tofs += base;
 
     // load: per batch, all loads in flight, then LDS
     if (live) {
@@ -650,16 +717,21 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
                 }
             }
             // a diagonal run right after the block may ride in its epilogue
-            const bool erun = (op.flags & BLK_RUN) != 0;
+            const int erun = !(op.flags & BLK_RUN) ? 0 : (ops[oi + 1].flags & DRUN_SIGNS) ? 2 : 1;
+            const TOp* run = &ops[oi + 1];
             switch (op.k) {
                 case 3:
-                    if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 16, L, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base); break; }
+                    if constexpr (sizeof(R) == 4 && L == 13) {
+                        if (erun == 2) { tile_block<R, 16, L, 2>(lds, ldsA, fa, op, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op, blob, L, run); break; }
+                    }
                     tile_block<R, 16, L>(lds, ldsA, fa, op, blob, L);
                     break;
                 case 4:
-                    if constexpr (sizeof(R) == 4 && L == 13)
-                        if (erun) { tile_block<R, 32, L, true>(lds, ldsA, fa, op, blob, L, &ops[oi + 1], base); break; }
+                    if constexpr (sizeof(R) == 4 && L == 13) {
+                        if (erun == 2) { tile_block<R, 32, L, 2>(lds, ldsA, fa, op, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op, blob, L, run); break; }
+                    }
                     tile_block<R, 32, L>(lds, ldsA, fa, op, blob, L);
                     break;
                 case 5: tile_block<R, 64, L>(lds, ldsA, fa, op, blob, L); break;
@@ -702,11 +774,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
         if (live) tofs = base + ldoff[(EP * tid) >> C] + ((EP * tid) & CM);
     }
     if (live) {
-        const uint32_t* __restrict__ rmhi = (const uint32_t*)(blob + pd.rmhi);
-        const uint32_t* __restrict__ rmlo = (const uint32_t*)(blob + pd.rmlo);
-        const bool remap = pd.remap != 0;
-        uint32_t rh0 = 0, rl0 = 0, rl1 = 0;     // the thread's remap entries
-        if (remap) {
+        if (MODE != 4 && remap) {               // the thread's remap entries
             rh0 = rmhi[e0 >> C];
             rl0 = rmlo[e0 & CM];
             rl1 = EP == 2 ? rmlo[(e0 + 1) & CM] : 0u;

@@ -125,7 +125,7 @@ static_assert(sizeof(DSub) == 64, "DSub is read as four 16-byte words");
 // subset-sum over the element bits gives element i the total of every group
 // S contained in i.  A condition h_j = 0 on an element bit is rewritten as
 // 1 - h_j on the host, so every term's element condition is a set of ones.
-// A DRUN_EPILOGUE run uses the same records over the layout of the block
+// A DRUN_EPILOGUE run uses ETerm records over the layout of the block
 // before it instead (thread code threadIdx.x, four element-code bits; the
 // block kernel documents which tile bits those are).
 struct DTerm {
@@ -134,6 +134,25 @@ struct DTerm {
     uint32_t lmask, lval;   // thread bits only
 };
 static_assert(sizeof(DTerm) == 32, "DTerm layout");
+
+// One term of a diagonal run applied in a block's epilogue (DRUN_EPILOGUE,
+// complex64): the DTerm condition with the tile's outer-bit test taken over
+// the workgroup index (the tile index, whose bits are the non-tile physical
+// bits in ascending order), so that every field is 32 bits.  A term matches
+// thread t of tile w when (w & om) == ov and (t & lm) == lv, and element code
+// i when i contains its group's element bits.  w holds the term's angle in
+// turns of 2^-32 for a phase run; for a sign run (every term a factor of
+// -1) the element codes it flips: the codes that contain its group.  The
+// records are stored by group with offsets (17 words, TOp::tab); each
+// group is padded to an even count with a record that never matches
+// (om = 0, ov = 1), as the kernel reads two records per scalar load.
+struct ETerm {
+    uint32_t om, ov;
+    uint32_t lm, lv;
+    uint32_t w;
+    uint32_t pad_[3];       // 32 bytes: two records per 64-byte scalar load
+};
+static_assert(sizeof(ETerm) == 32, "ETerm layout");
 
 struct PassDesc {
     int32_t L;              // tile qubits

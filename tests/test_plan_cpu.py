@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import _DSUB, _DTERM, _TOP, blocks_and_diagonals, plan_image
+from tests.util import (_DSUB, _DTERM, _ETERM, _TOP, blocks_and_diagonals, plan_image,
+                        tile_blocks_outer_diagonals)
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit,
                        random_mixed_circuit, random_planner_circuit)
 
@@ -194,12 +195,13 @@ def test_plan_flags_rejected():
 
 def run_angles(terms, off, t, nhb, wmask):
     """Angle-path sums: per element code i and thread code t, the total of
-    every term group whose element-bit set is contained in i."""
+    every term group whose element-bit set is contained in i (terms whose
+    outer-bit test holds for the tile: the caller passes only those)."""
     assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) >= 0)
     acc = np.zeros((1 << nhb, len(t)), np.uint64)
     for g in range(1 << nhb):
         for d in terms[off[g]: off[g + 1]]:
-            assert d["oval"] == 0 and d["lmask"] < 512 and d["lval"] & ~d["lmask"] == 0
+            assert d["lmask"] < 512 and d["lval"] & ~d["lmask"] == 0
             hit = (t & np.uint64(d["lmask"])) == np.uint64(d["lval"])
             acc[g] = (acc[g] + np.where(hit, d["turns"], np.uint64(0))) & wmask
     for b in range(nhb):
@@ -408,72 +410,124 @@ def test_block_layouts_and_wave_ownership(k_max, tile, dtype):
     check_block_layouts(qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile), dtype)
 
 
-@pytest.mark.parametrize("k_max", [3, 4])
-def test_epilogue_runs_reproduce_the_circuit(k_max):
+def deposit(w, qmask):
+    """Tile index w with a zero inserted at every tile bit (set bit of
+    qmask): the tile's base physical index."""
+    out, j = 0, 0
+    for p in range(64):
+        if (qmask >> p) & 1:
+            continue
+        out |= ((w >> j) & 1) << p
+        j += 1
+        if w >> j == 0:
+            break
+    return out
+
+
+def epilogue_factors(terms, off, w, signs):
+    """Factors of a run applied in a block's epilogue, per (element code,
+    thread code), for tile index w: records matched on the tile index and
+    the thread, sign runs as parities over the element codes each record
+    lists, phase runs as grouped angle sums and subset sums."""
+    t = np.arange(512, dtype=np.int64)
+    assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) % 2 == 0)
+    hit = lambda d: ((w & int(d["om"])) == int(d["ov"])) & ((t & int(d["lm"])) == int(d["lv"]))
+    if signs:
+        m = np.zeros(512, np.int64)
+        for d in terms:
+            m ^= np.where(hit(d), int(d["w"]), 0)
+        flips = (m[None, :] >> np.arange(16)[:, None]) & 1
+        return np.where(flips == 1, -1.0, 1.0)
+    acc = np.zeros((16, 512), np.uint64)
+    for g in range(16):
+        for d in terms[off[g]: off[g + 1]]:
+            acc[g] = (acc[g] + np.where(hit(d), np.uint64(int(d["w"])), np.uint64(0))) & np.uint64(0xFFFFFFFF)
+    for b in range(4):
+        for i in range(16):
+            if (i >> b) & 1:
+                acc[i] = (acc[i] + acc[i ^ (1 << b)]) & np.uint64(0xFFFFFFFF)
+    return np.exp(2j * np.pi * (acc.astype(np.float64) / 2.0 ** 32))
+
+
+@pytest.mark.parametrize("n,k_max,signs", [(13, 3, False), (13, 4, False), (15, 3, False), (15, 4, False),
+                                           (15, 3, True), (15, 4, True)])
+def test_epilogue_runs_reproduce_the_circuit(n, k_max, signs):
     """Pins the encoding of diagonal runs that a complex64 block applies to
-    its outputs (13-qubit tiles): emulating the single pass op by op from the
-    plan image (blocks through their address tables and matrices, runs from
-    their terms over the block epilogue's layout or the standalone layout)
+    its outputs (13-qubit tiles; with 15 qubits the runs' gates also act on
+    the two qubits outside the tile, so their terms test the tile index):
+    emulating the single pass tile by tile and op by op from the plan image
+    (blocks through their address tables and matrices, runs from their
+    records over the block epilogue's layout or the standalone layout)
     gives the oracle's state of the whole circuit."""
-    n = 13
-    rng = np.random.Generator(np.random.PCG64(4100 + k_max))
-    gates = blocks_and_diagonals(n, 4100 + k_max)
-    plan = qvm.Plan(gates, n, "c64", k_max=k_max, tile_qubits=n)
+    L = 13
+    seed = 4100 + 10 * n + k_max + 100 * signs
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = (blocks_and_diagonals(n, seed, signs_only=signs) if n == L
+             else tile_blocks_outer_diagonals(L, n, seed, signs_only=signs))
+    plan = qvm.Plan(gates, n, "c64", k_max=k_max, tile_qubits=L)
     rec, passes = plan_image(plan)
-    assert len(passes) == 1 and passes[0]["remap"] == 0
+    assert len(passes) == 1 and passes[0]["remap"] == 0 and passes[0]["L"] == L
     pd = passes[0]
-    c = int(pd["c"])
-    ldoff = rec(int(pd["ldoff"]), np.dtype("<u8"), 1 << (n - c))
-    e = np.arange(1 << n, dtype=np.uint64)
-    phys = ((e & np.uint64((1 << c) - 1)) | ldoff[(e >> np.uint64(c)).astype(np.int64)]).astype(np.int64)
+    c, qmask = int(pd["c"]), int(pd["qmask"])
+    ldoff = rec(int(pd["ldoff"]), np.dtype("<u8"), 1 << (L - c))
+    e = np.arange(1 << L, dtype=np.uint64)
+    local = ((e & np.uint64((1 << c) - 1)) | ldoff[(e >> np.uint64(c)).astype(np.int64)]).astype(np.int64)
     psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
     psi0 /= np.linalg.norm(psi0)
-    tile = psi0[phys].copy()
-    wmask = np.uint64(0xFFFFFFFF)
-    t = np.arange(512, dtype=np.uint64)
-    nb, n_epi, n_sync, prev = 0, 0, 0, None
-    for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
-        if op["type"] == 1:
-            blk = plan.block(nb)
-            nb += 1
-            assert blk["k"] == op["k"]
-            n_sync += bool(op["flags"] & 2)
-            ins, outs, _, epi_map = block_layout(rec, op, n, "c64")
-            x = tile[ins]                               # columns of the block's input
-            tile[outs] = x @ np.asarray(blk["matrix"]).T
-            prev = (op, epi_map)
-            continue
-        if op["flags"] & 1:
-            epi = bool(op["flags"] & 4)
-            nhb = 4
-            terms = rec(int(op["data"]), _DTERM, int(op["k"]))
-            off = rec(int(op["tab"]), np.dtype("<u4"), (1 << nhb) + 1)
-            ang = run_angles(terms, off, t, nhb, wmask)
-            if epi:
-                n_epi += 1
+    got = np.zeros(1 << n, np.complex128)
+    ops = rec(int(pd["ops"]), _TOP, int(pd["nops"]))
+    n_epi = n_sign = 0
+    for w in range(1 << (n - L)):
+        base = deposit(w, qmask)
+        phys = base | local
+        tile = psi0[phys].copy()
+        nb, prev = 0, None
+        for op in ops:
+            if op["type"] == 1:
+                blk = plan.block(nb)
+                nb += 1
+                assert blk["k"] == op["k"]
+                ins, outs, _, epi_map = block_layout(rec, op, L, "c64")
+                x = tile[ins]                           # columns of the block's input
+                tile[outs] = x @ np.asarray(blk["matrix"]).T
+                prev = (op, epi_map)
+                continue
+            if op["flags"] & 4:
+                # applied in the preceding block's epilogue
                 assert prev is not None and prev[0]["flags"] & 1
+                off = rec(int(op["tab"]), np.dtype("<u4"), 17)
+                terms = rec(int(op["data"]), _ETERM, int(off[-1]))
+                f = epilogue_factors(terms, off, w, bool(op["flags"] & 2))
+                n_epi += w == 0
+                n_sign += w == 0 and bool(op["flags"] & 2)
                 epi_map = prev[1]
                 where = np.full((16, 512), -1, np.int64)
                 where[epi_map[:, 1], epi_map[:, 0]] = epi_map[:, 2]
+                fac = np.zeros(1 << L, np.complex128)
+                fac[where.reshape(-1)] = f.reshape(-1)
+                assert np.all(fac != 0)           # every element gets exactly one factor
+                tile *= fac
+            elif op["flags"] & 1:
+                terms = rec(int(op["data"]), _DTERM, int(op["k"]))
+                off = rec(int(op["tab"]), np.dtype("<u4"), 17)
+                t = np.arange(512, dtype=np.uint64)
+                live = terms[(np.uint64(base) & terms["omask"]) == terms["oval"]]
+                # the standalone layout: element t + 512 i
+                offs = np.searchsorted(np.flatnonzero((np.uint64(base) & terms["omask"]) == terms["oval"]), off)
+                ang = run_angles(live, offs.astype(np.uint32), t, 4, np.uint64(0xFFFFFFFF)).reshape(-1)
+                f = (np.where(ang >> np.uint64(31), -1.0, 1.0) if op["flags"] & 2
+                     else np.exp(2j * np.pi * (ang.astype(np.float64) / 2.0 ** 32)))
+                tile *= f
             else:
-                where = (np.arange(16)[:, None] * 512 + np.arange(512)[None, :])
-            if op["flags"] & 2:
-                f = np.where(ang >> np.uint64(31), -1.0, 1.0)
-            else:
-                f = np.exp(2j * np.pi * (ang.astype(np.float64) / 2.0 ** 32))
-            fac = np.zeros(1 << n, np.complex128)
-            fac[where.reshape(-1)] = f.reshape(-1)
-            assert np.all(fac != 0)           # every element gets exactly one factor
-            tile *= fac
-        else:
-            for d in rec(int(op["data"]), _DSUB, int(op["k"])):
-                hit = (e & np.uint64(d["lmask"])) == np.uint64(d["lval"])
-                f = -1.0 if d["neg"] else d["pr"] + 1j * d["pi"]
-                tile = np.where(hit, tile * f, tile)
-        prev = None
-    assert nb == plan.stats()["blocks"] and n_epi >= 1
-    got = np.zeros(1 << n, np.complex128)
-    got[phys] = tile
+                for d in rec(int(op["data"]), _DSUB, int(op["k"])):
+                    hit = ((e & np.uint64(d["lmask"])) == np.uint64(d["lval"])) & \
+                        ((base & int(d["omask"])) == int(d["oval"]))
+                    f = -1.0 if d["neg"] else d["pr"] + 1j * d["pi"]
+                    tile = np.where(hit, tile * f, tile)
+            prev = None
+        assert nb == plan.stats()["blocks"]
+        got[phys] = tile
+    assert n_epi >= 1 and (n_sign >= 1 or not signs)
     want = oracle.apply_gates(psi0.copy(), n, gates)
     assert np.max(np.abs(got - want)) < 1e-7
 

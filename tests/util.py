@@ -46,6 +46,7 @@ _TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"
 _DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
                   ("oval", "<u8"), ("pr", "<f8"), ("pi", "<f8"), ("turns", "<u8"), ("pad", "<u8")])
 _DTERM = np.dtype([("omask", "<u8"), ("oval", "<u8"), ("turns", "<u8"), ("lmask", "<u4"), ("lval", "<u4")])
+_ETERM = np.dtype([("om", "<u4"), ("ov", "<u4"), ("lm", "<u4"), ("lv", "<u4"), ("w", "<u4"), ("pad", "<u4", 3)])
 
 
 def plan_image(plan):
@@ -83,6 +84,29 @@ def blocks_and_diagonals(n, seed, layers=14, signs_only=False):
     for _ in range(layers):
         for _ in range(3):
             a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            th = float(rng.uniform(0, 2 * np.pi))
+            gates.append([Gate("h", (a,)), Gate("rx", (a,), (), (th,)), Gate("x", (a,), (b,))][int(rng.integers(0, 3))])
+        for _ in range(int(rng.integers(2, 9))):
+            a, b = (int(v) for v in rng.choice(n, 2, replace=False))
+            th = float(rng.uniform(0, 2 * np.pi))
+            if signs_only:
+                gates.append([Gate("z", (a,), (b,)), Gate("z", (a,))][int(rng.integers(0, 2))])
+                continue
+            gates.append([Gate("rz", (a,), (), (th,)), Gate("z", (a,), (b,)), Gate("p", (a,), (b,), (th,)),
+                          Gate("rzz", (a, b), (), (th,)), Gate("t", (a,))][int(rng.integers(0, 5))])
+    return gates
+
+
+def tile_blocks_outer_diagonals(n_tile, n, seed, layers=14, signs_only=False):
+    """blocks_and_diagonals with the dense gates on qubits below n_tile and
+    the diagonal gates on any of the n qubits: one pass of n_tile-qubit
+    tiles whose diagonal runs test the tile's outer bits."""
+    from workloads import Gate
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = []
+    for _ in range(layers):
+        for _ in range(3):
+            a, b = (int(v) for v in rng.choice(n_tile, 2, replace=False))
             th = float(rng.uniform(0, 2 * np.pi))
             gates.append([Gate("h", (a,)), Gate("rx", (a,), (), (th,)), Gate("x", (a,), (b,))][int(rng.integers(0, 3))])
         for _ in range(int(rng.integers(2, 9))):
