@@ -458,8 +458,33 @@ ColMap col_map(const int32_t* lb, int k, int L, qvm_dtype dt, uint32_t W) {
         if (!((bmask >> b) & 1) && !((W >> b) & 1)) rest.push_back(b);
     ColMap m;
     m.nlane = std::min(4, (int)rest.size());
-    for (int i = 0; i < m.nlane; ++i) m.lane[i] = rest[i];
-    rest.erase(rest.begin(), rest.begin() + m.nlane);
+    // lane bits: the lowest free bits whose slots are independent in the
+    // low slot bits that select the LDS bank (complex64: bits 0..3, the 16
+    // lanes of a 64-bit access; complex128: bits 0..2, the 8 lanes of a
+    // 128-bit access, lane bits 0..2), picked greedily (a basis of the
+    // widest span, lowest bits first), then the lowest remaining bits
+    const uint32_t bank = dt == QVM_C128 ? 7u : 15u;
+    const int nind = dt == QVM_C128 ? 3 : 4;
+    std::vector<int> pick;
+    uint32_t basis[4] = {0, 0, 0, 0};         // reduced images, by leading bit
+    for (int b : rest) {
+        if ((int)pick.size() >= std::min(nind, m.nlane)) break;
+        uint32_t v = tile_swizzle(1u << b) & bank;
+        for (int j = 3; j >= 0 && v; --j)
+            if ((v >> j) & 1) {
+                if (!basis[j]) break;
+                v ^= basis[j];
+            }
+        if (!v) continue;
+        int lead = 31 - __builtin_clz(v);
+        basis[lead] = v;
+        pick.push_back(b);
+    }
+    for (int b : rest)
+        if ((int)pick.size() < m.nlane && std::find(pick.begin(), pick.end(), b) == pick.end()) pick.push_back(b);
+    std::sort(pick.begin(), pick.begin() + std::min((int)pick.size(), nind));
+    for (int i = 0; i < m.nlane; ++i) m.lane[i] = pick[i];
+    for (int i = 0; i < m.nlane; ++i) rest.erase(std::find(rest.begin(), rest.end(), pick[i]));
     if (!W) {
         m.tib = rest;
         return m;
@@ -1102,17 +1127,19 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 std::vector<int> src(L);
                 for (int d = 0; d < L; ++d) src[d] = local_of_wire[newat[d]];
                 std::vector<uint32_t> hi((size_t)1 << (L - c)), lo((size_t)1 << c);
+                // entries are LDS slots of the source elements (the swizzle
+                // is linear, so the slot of hi | lo is the XOR of the two)
                 for (size_t v = 0; v < hi.size(); ++v) {
                     uint32_t e = 0;
                     for (int d = c; d < L; ++d)
                         if ((v >> (d - c)) & 1) e |= 1u << src[d];
-                    hi[v] = e;
+                    hi[v] = tile_swizzle(e);
                 }
                 for (size_t v = 0; v < lo.size(); ++v) {
                     uint32_t e = 0;
                     for (int d = 0; d < c; ++d)
                         if ((v >> d) & 1) e |= 1u << src[d];
-                    lo[v] = e;
+                    lo[v] = tile_swizzle(e);
                 }
                 pd.remap = 1;
                 pd.rmhi = B.put(hi.data(), hi.size() * sizeof(uint32_t));

@@ -65,6 +65,19 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 
 __device__ __forceinline__ uint32_t sw(uint32_t e) { return tile_swizzle(e); }
 
+// A 16-byte piece of two complex64 elements (2m, 2m + 1) as it sits in LDS:
+// at the slot pair of sw(2m), swapped when that slot is odd (the swizzle
+// keeps the pair adjacent but may reverse it).  Its own inverse.
+template <int EP, typename V>
+__device__ __forceinline__ V pair_order(V v, uint32_t s) {
+    if constexpr (EP == 2) {
+        const bool odd = (s & 1u) != 0;
+        return odd ? V{v[2], v[3], v[0], v[1]} : v;
+    } else {
+        return v;
+    }
+}
+
 // w with a zero inserted at every set bit of `fixed` (the tile bits), one
 // run of consecutive set bits at a time: the tile's base index from its
 // workgroup index.
@@ -455,13 +468,14 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
     constexpr uint32_t LOWM = NT - 1;
     const uint32_t t = threadIdx.x;
     const bool live = t < nE;
+    const uint32_t swt = sw(t);          // slots are linear: sw(t + NT i) = sw(t) ^ sw(NT i)
 #pragma unroll 1
     for (int i0 = 0; i0 < NROW; i0 += NPT) {
         R xr[NPT], xi[NPT];
         if (live) {
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
-                const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+                const uint32_t s = 2 * (swt ^ sw(NT * (uint32_t)(i0 + i)));
                 xr[i] = lds[s];
                 xi[i] = lds[s + 1];
             }
@@ -499,7 +513,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
         if (live) {
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
-                const uint32_t s = 2 * sw(t + NT * (uint32_t)(i0 + i));
+                const uint32_t s = 2 * (swt ^ sw(NT * (uint32_t)(i0 + i)));
                 lds[s] = xr[i];
                 lds[s + 1] = xi[i];
             }
@@ -519,9 +533,10 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     TU acc[NE];
     run_angles<TU, NHB>(acc, terms, grp, base, t);
     if (t >= nE) return;
+    const uint32_t swt = sw(t);
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        const uint32_t e = 2 * sw(t + NT * (uint32_t)i);
+        const uint32_t e = 2 * (swt ^ sw(NT * (uint32_t)i));
         const R xr = lds[e], xi = lds[e + 1];
         if (signs) {
             // the accumulated angle is 0 or a half turn
@@ -648,13 +663,14 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     const bool remap = pd.remap != 0;
     const uint32_t e0 = EP * threadIdx.x;
     // the thread's table entries first (the tile loads wait for them only):
-    // its chunk offset and, in passes with few fragment registers, its remap
-    // entries for the store phase
+    // its chunk offset and, in complex64 passes with few fragment registers,
+    // its remap entries for the store phase
+    constexpr bool PRE_RM = MODE == 4 && EP == 2;
     uint64_t tofs = 0;
     uint32_t rh0 = 0, rl0 = 0, rl1 = 0;
     if (live) {
         tofs = ldoff[e0 >> C] + (e0 & CM);
-        if (MODE == 4 && remap) {
+        if (PRE_RM && remap) {
             rh0 = rmhi[e0 >> C];
             rl0 = rmlo[e0 & CM];
             rl1 = EP == 2 ? rmlo[(e0 + 1) & CM] : 0u;
@@ -667,7 +683,10 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     // the thread's piece offsets: its table entry plus the uniform one of i
     tofs += base;
 
-    // load: per batch, all loads in flight, then LDS
+    // load: per batch, all loads in flight, then LDS.  The slot of piece i
+    // is the thread's slot XOR a constant (the swizzle is linear and the
+    // thread's bits and i's are disjoint).
+    const uint32_t se0 = sw(e0);
     if (live) {
 #pragma unroll
         for (int b0 = 0; b0 < NIT; b0 += BATCH) {
@@ -677,8 +696,8 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
                 v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * (tofs + ldoff[HI * (b0 + it)])));
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
-                const uint32_t e = e0 + (uint32_t)EP * NT * (uint32_t)(b0 + it);
-                *(V16*)(lds + 2 * sw(e)) = v[it];
+                const uint32_t s = se0 ^ sw((uint32_t)EP * NT * (uint32_t)(b0 + it));
+                *(V16*)(lds + 2 * (s & ~(uint32_t)(EP - 1))) = pair_order<EP>(v[it], s);
             }
         }
     }
@@ -773,8 +792,12 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
         asm volatile("" : "+v"(tid));
         if (live) tofs = base + ldoff[(EP * tid) >> C] + ((EP * tid) & CM);
     }
+    // the thread's first slot, formed again (not kept through the ops)
+    uint32_t e0s = e0;
+    asm volatile("" : "+v"(e0s));
+    const uint32_t ss0 = sw(e0s);
     if (live) {
-        if (MODE != 4 && remap) {               // the thread's remap entries
+        if (!PRE_RM && remap) {                 // the thread's remap entries
             rh0 = rmhi[e0 >> C];
             rl0 = rmlo[e0 & CM];
             rl1 = EP == 2 ? rmlo[(e0 + 1) & CM] : 0u;
@@ -785,16 +808,17 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
             if (!remap) {
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t d = e0 + (uint32_t)EP * NT * (uint32_t)(b0 + it);
-                    v[it] = *(const V16*)(lds + 2 * sw(d));
+                    const uint32_t s = ss0 ^ sw((uint32_t)EP * NT * (uint32_t)(b0 + it));
+                    v[it] = pair_order<EP>(*(const V16*)(lds + 2 * (s & ~(uint32_t)(EP - 1))), s);
                 }
             } else {
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t hi = rh0 | rmhi[HI * (b0 + it)];
-                    const uint32_t s0 = 2 * sw(hi | rl0);
+                    // the tables hold slots: disjoint bits, so their XOR is the slot
+                    const uint32_t hi = rh0 ^ rmhi[HI * (b0 + it)];
+                    const uint32_t s0 = 2 * (hi ^ rl0);
                     if constexpr (EP == 2) {
-                        const uint32_t s1 = 2 * sw(hi | rl1);
+                        const uint32_t s1 = 2 * (hi ^ rl1);
                         v[it] = V16{lds[s0], lds[s0 + 1], lds[s1], lds[s1 + 1]};
                     } else {
                         v[it] = V16{lds[s0], lds[s0 + 1]};
@@ -808,9 +832,11 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     }
 }
 
-// One kernel per fragment mode, so that each gets its own register budget.
+// One kernel per fragment mode, so that each gets its own register budget:
+// four waves per SIMD (two workgroups per CU) where the tile leaves room
+// for two workgroups in LDS and the registers allow it.
 template <typename R, int L, int MODE>
-__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
+__global__ __launch_bounds__(NT, (sizeof(R) == 4 || (MODE == 4 && L <= 12)) ? 4 : 2) void k_tile(R* __restrict__ psi, PassDesc pd,
                                                  const char* __restrict__ blob) {
     tile_pass<R, L, MODE>(psi, pd, blob);
 }

@@ -41,12 +41,19 @@ struct TOp {
                             // angle-path diagonal run: byte offset of its group offsets
 };
 
-// LDS slot of tile element e: bits 1..3 are XOR-ed with bits 4..6 and 8..10
-// so that column walks with large strides spread over banks; bit 0 is kept,
-// so pairs (2m, 2m+1) stay adjacent for 16-byte accesses.  The map is linear
-// over GF(2): slot(a ^ b) = slot(a) ^ slot(b).
-__host__ __device__ inline uint32_t tile_swizzle(uint32_t e) {
-    return e ^ ((((e >> 4) ^ (e >> 8)) & 7u) << 1);
+// LDS slot of tile element e: the four low bits are XOR-ed with a fixed
+// image of every bit above them (bits 4..12 contribute 3, 5, 6, 9, 10, 12,
+// 7, 11, 13: distinct vectors of weight two or three), so that for every
+// block the planner can choose four column bits whose slots differ in the
+// low bits that select the LDS bank (a 16-lane column walk then hits
+// distinct banks).  The map is linear over GF(2) (slot(a ^ b) = slot(a) ^
+// slot(b)) and an involution (the bits above 3 are unchanged); elements 2m
+// and 2m + 1 keep adjacent slots, in either order (slot bit 0).
+__host__ __device__ constexpr uint32_t tile_swizzle(uint32_t e) {
+    constexpr uint32_t img[9] = {3, 5, 6, 9, 10, 12, 7, 11, 13};
+    uint32_t x = 0;
+    for (int j = 0; j < 9; ++j) x ^= ((e >> (4 + j)) & 1u) ? img[j] : 0u;
+    return e ^ x;
 }
 
 // Address table of a block op (uint32 words, byte offsets into the tile:
@@ -164,8 +171,8 @@ struct PassDesc {
     uint64_t qmask;         // physical bits that are tile bits
     uint64_t ops;           // byte offset of TOp[nops]
     uint64_t ldoff;         // byte offset of uint64 off[2^(L-c)]: chunk -> physical offset
-    uint64_t rmhi;          // byte offset of uint32 tab[2^(L-c)]: remap of the high local bits
-    uint64_t rmlo;          // byte offset of uint32 tab[2^c]: remap of the low local bits
+    uint64_t rmhi;          // byte offset of uint32 tab[2^(L-c)]: LDS slot of the remapped high local bits
+    uint64_t rmlo;          // byte offset of uint32 tab[2^c]: LDS slot of the remapped low local bits
 };
 
 }  // namespace qvm

@@ -276,10 +276,50 @@ def test_angle_path_encoding_reproduces_diagonal(dtype, n):
         assert np.max(np.abs(got - want)) < tol, (only_signs, np.max(np.abs(got - want)))
 
 
+_SWZ_IMG = (3, 5, 6, 9, 10, 12, 7, 11, 13)     # low-bit images of tile bits 4..12
+
+
 def _swz(e):
     """The tile kernel's LDS swizzle (an involution: it is its own inverse)."""
     e = np.asarray(e, dtype=np.int64)
-    return e ^ ((((e >> 4) ^ (e >> 8)) & 7) << 1)
+    x = np.zeros_like(e)
+    for j, v in enumerate(_SWZ_IMG):
+        x ^= np.where((e >> (4 + j)) & 1, v, 0)
+    return e ^ x
+
+
+def test_swizzle_is_a_linear_involution_and_spreads_banks():
+    """The LDS slot map: an involution on every tile size, linear over
+    GF(2), element pairs (2m, 2m + 1) on adjacent slots; and the column bits
+    the planner gives the lanes of the 30-qubit workload's blocks put every
+    16-lane column walk of complex64 on distinct LDS bank pairs (slot bits
+    0..3) whenever the free bits allow it (they do for every block there)."""
+    for L in range(3, 14):
+        e = np.arange(1 << L)
+        s = _swz(e)
+        assert np.array_equal(np.sort(s), e) and np.array_equal(_swz(s), e)
+        a, b = e[:, None], e[None, ::97]
+        assert np.array_equal(_swz(a ^ b), _swz(a) ^ _swz(b))
+        assert np.all((s[0::2] ^ s[1::2]) == 1)
+    cfg = config_circuit("qft30")
+    plan = qvm.Plan(cfg["gates"], 30, "c64", k_max=3, tile_qubits=13)
+    rec, passes = plan_image(plan)
+    nblk = 0
+    for pd in passes:
+        L = int(pd["L"])
+        for op in rec(int(pd["ops"]), _TOP, int(pd["nops"])):
+            if op["type"] != 1:
+                continue
+            k = int(op["k"])
+            ntile, K = ((1 << (L - k)) + 15) >> 4, 2 << k
+            off = ntile + K // 8 + 4 * (K // 16)
+            lanew = rec(int(op["tab"]), np.dtype("<u4"), off + 4)[off:]
+            slots = [0]
+            for w in lanew:
+                slots = slots + [x ^ (int(w) // 8) for x in slots]
+            assert len({x & 15 for x in slots}) == 16, (k, lanew)
+            nblk += 1
+    assert nblk == plan.stats()["blocks"]
 
 
 def _block_ct(k, L, c128):
