@@ -848,7 +848,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 }
                 op.k = (int32_t)terms.size();
                 op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0) | DRUN_EPILOGUE;
-                ops.back().flags |= BLK_RUN;
+                ops.back().flags |= BLK_RUN | (signs ? BLK_RUN_SIGNS : 0);
                 epi_runs.emplace_back(ops.size(), std::move(run));
                 run.clear();
             } else if ((int)run.size() >= at_least) {
@@ -1049,6 +1049,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         pd.first_block = -1;
         for (int oi = (int)ops.size() - 1; oi >= 0; --oi) {
             ops[oi].next_block = pd.first_block;
+            ops[oi].next_data = pd.first_block >= 0 ? ops[pd.first_block].data : 0;
             if (ops[oi].type == TOP_BLOCK) {
                 pd.first_block = oi;
                 pd.kmax = std::max(pd.kmax, (int32_t)ops[oi].k);

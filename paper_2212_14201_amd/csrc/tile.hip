@@ -286,8 +286,8 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // block ahead) instead of the LDS fragment area.
 template <typename R, int K, int LT, int RUN = 0, bool GA = false, int NF = 1>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NF],
-                                           const TOp& op, const char* __restrict__ blob, int L_,
-                                           const TOp* __restrict__ run = nullptr) {
+                                           uint64_t tab_off, const char* __restrict__ blob, int L_,
+                                           const TOp* __restrict__ run = nullptr, int wave_ = -1) {
     static_assert(RUN == 0 || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
     constexpr int L = LT;                      // the kernel's tile width
@@ -306,7 +306,8 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     constexpr int CT = block_ct(k, LT, sizeof(R) == 8);
     static_assert(!GA || RB * KS <= NF, "register fragments: the block's share fits the registers");
     // the wave index as a scalar, so the column table reads below are scalar loads
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_ >= 0 ? wave_ : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int ncol = L >= k ? 1 << (L - k) : 1;
     constexpr int ntile = (ncol + 15) >> 4;
     // every wave takes whole column tiles of full columns: no bounds tests
@@ -320,7 +321,12 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     constexpr uint32_t ES = 2 * sizeof(R);     // bytes per amplitude
     (void)lds;
     const BlockTabLayout lay(L, k);
-    const uint32_t* __restrict__ tab = (const uint32_t*)(blob + op.tab);
+    const uint32_t* __restrict__ tab = (const uint32_t*)(blob + tab_off);
+    // one column iteration per wave: its column tiles' words are loaded with
+    // the others, so the block waits for its table once
+    constexpr bool ONE = FULL && ntile == NW * CT;
+    uint32_t cw1[CT];
+    if constexpr (ONE) sload<CT>(cw1, tab + lay.col() + wave * CT);
     // the block's uniform words that do not depend on the column tile,
     // each group in one scalar load
     constexpr int NBW = KS / 2, NEW = 4 * RB;
@@ -361,7 +367,9 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
 #pragma unroll
         for (int i = 0; i < NA; ++i) afr[i] = GA ? fa[i] : Arow[i * 64];
     }
-    for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) {
+    // one wave iteration over CT column tiles from t0 (no loop where there
+    // is one iteration, so the table loads above are issued together)
+    auto columns = [&](const int t0) {
         uint32_t cw[CT];                       // column tiles' slots (uniform)
         bool ok[CT];
 #pragma unroll
@@ -374,7 +382,12 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                 cw[ct] = tab[lay.col() + min(t0 + ct, ntile - 1)];
             }
         }
-        if constexpr (FULL) sload<CT>(cw, tab + lay.col() + t0);
+        if constexpr (ONE) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) cw[ct] = cw1[ct];
+        } else if constexpr (FULL) {
+            sload<CT>(cw, tab + lay.col() + t0);
+        }
         V4 acc[CT][RB];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
@@ -449,6 +462,11 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                 }
             }
         }
+    };
+    if constexpr (ONE) {
+        columns(wave * CT);
+    } else {
+        for (int t0 = wave * CT; t0 < ntile; t0 += NW * CT) columns(t0);
     }
 }
 
@@ -567,8 +585,8 @@ __device__ __forceinline__ void wave_lds_order() {
 // flight are known at every point and waiting for one block's fragments
 // never waits for the next block's.
 template <typename R, int NF>
-__device__ __forceinline__ void fetch_frag(R (&dst)[NF], const TOp& b, const char* __restrict__ blob) {
-    const R* __restrict__ f = (const R*)(blob + b.data) + (threadIdx.x & 63);
+__device__ __forceinline__ void fetch_frag(R (&dst)[NF], uint64_t data, const char* __restrict__ blob) {
+    const R* __restrict__ f = (const R*)(blob + data) + (threadIdx.x & 63);
 #pragma unroll
     for (int i = 0; i < NF; ++i) dst[i] = f[64 * i];
 }
@@ -581,40 +599,46 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
                                                  const char* __restrict__ blob, uint64_t base, R (&fa)[NF]) {
     R fb[NF];
     bool first = true;           // the barrier after the load phase covers the first op
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int oi = 0; oi < pd.nops; ++oi) {
-        const TOp& op = ops[oi];
-        if (op.type != TOP_BLOCK && (op.flags & DRUN_EPILOGUE)) continue;   // applied by the block before it
+        // the whole op record in one scalar load (one wait per op)
+        uint32_t r[16];
+        sload<16>(r, (const uint32_t*)(ops + oi));
+        const int32_t type = (int32_t)r[0], k = (int32_t)r[1], flags = (int32_t)r[11];
+        const uint64_t data = r[8] | (uint64_t)r[9] << 32, tab = r[12] | (uint64_t)r[13] << 32;
+        const uint64_t next_data = r[14] | (uint64_t)r[15] << 32;
+        const bool has_next = (int32_t)r[10] >= 0;
+        if (type != TOP_BLOCK && (flags & DRUN_EPILOGUE)) continue;   // applied by the block before it
         if (!first) {
-            if (op.type == TOP_BLOCK && (op.flags & BLK_NOSYNC)) wave_lds_order();
+            if (type == TOP_BLOCK && (flags & BLK_NOSYNC)) wave_lds_order();
             else __syncthreads();
         }
         first = false;
-        if (op.type == TOP_BLOCK) {
-            const int nb = op.next_block;
-            if (nb >= 0) fetch_frag<R, NF>(fb, ops[nb], blob);
+        if (type == TOP_BLOCK) {
+            if (has_next) fetch_frag<R, NF>(fb, next_data, blob);
             // a diagonal run right after the block may ride in its epilogue
             constexpr bool RUNOK = sizeof(R) == 4 && L == 13;
             constexpr int RP = RUNOK ? 1 : 0, RS = RUNOK ? 2 : 0;
-            const int erun = !RUNOK || !(op.flags & BLK_RUN) ? 0 : (ops[oi + 1].flags & DRUN_SIGNS) ? 2 : 1;
+            const int erun = !RUNOK || !(flags & BLK_RUN) ? 0 : (flags & BLK_RUN_SIGNS) ? 2 : 1;
             const TOp* run = &ops[oi + 1];
-            if (NF == 4 || op.k == 3) {
-                if (erun == 2) tile_block<R, 16, L, RS, true>(lds, lds, fa, op, blob, L, run);
-                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, op, blob, L, run);
-                else tile_block<R, 16, L, 0, true>(lds, lds, fa, op, blob, L);
+            if (NF == 4 || k == 3) {
+                if (erun == 2) tile_block<R, 16, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else tile_block<R, 16, L, 0, true>(lds, lds, fa, tab, blob, L, nullptr, wave);
             } else if constexpr (NF >= 16) {
-                if (erun == 2) tile_block<R, 32, L, RS, true>(lds, lds, fa, op, blob, L, run);
-                else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, op, blob, L, run);
-                else tile_block<R, 32, L, 0, true>(lds, lds, fa, op, blob, L);
+                if (erun == 2) tile_block<R, 32, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else tile_block<R, 32, L, 0, true>(lds, lds, fa, tab, blob, L, nullptr, wave);
             }
-            if (nb >= 0) {
+            if (has_next) {
 #pragma unroll
                 for (int i = 0; i < NF; ++i) fa[i] = fb[i];
             }
-        } else if (op.flags & DRUN_TURNS) {
-            tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + op.data), (const uint32_t*)(blob + op.tab), base,
-                                     (op.flags & DRUN_SIGNS) != 0);
+        } else if (flags & DRUN_TURNS) {
+            tile_diagrun_turns<R, L>(lds, (const DTerm*)(blob + data), (const uint32_t*)(blob + tab), base,
+                                     (flags & DRUN_SIGNS) != 0);
         } else {
-            tile_diagrun<R, L>(lds, (const DSub*)(blob + op.data), op.k, base);
+            tile_diagrun<R, L>(lds, (const DSub*)(blob + data), k, base);
         }
     }
     __syncthreads();
@@ -678,7 +702,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     }
     R fa[MODE > 0 ? MODE : 1];
     if constexpr (MODE > 0)
-        if (pd.first_block >= 0) fetch_frag<R, MODE>(fa, ops[pd.first_block], blob);
+        if (pd.first_block >= 0) fetch_frag<R, MODE>(fa, ops[pd.first_block].data, blob);
     const uint64_t base = dep64((uint64_t)blockIdx.x, pd.qmask);
     // the thread's piece offsets: its table entry plus the uniform one of i
     tofs += base;
@@ -741,20 +765,20 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
             switch (op.k) {
                 case 3:
                     if constexpr (sizeof(R) == 4 && L == 13) {
-                        if (erun == 2) { tile_block<R, 16, L, 2>(lds, ldsA, fa, op, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op, blob, L, run); break; }
+                        if (erun == 2) { tile_block<R, 16, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op.tab, blob, L, run); break; }
                     }
-                    tile_block<R, 16, L>(lds, ldsA, fa, op, blob, L);
+                    tile_block<R, 16, L>(lds, ldsA, fa, op.tab, blob, L);
                     break;
                 case 4:
                     if constexpr (sizeof(R) == 4 && L == 13) {
-                        if (erun == 2) { tile_block<R, 32, L, 2>(lds, ldsA, fa, op, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op, blob, L, run); break; }
+                        if (erun == 2) { tile_block<R, 32, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op.tab, blob, L, run); break; }
                     }
-                    tile_block<R, 32, L>(lds, ldsA, fa, op, blob, L);
+                    tile_block<R, 32, L>(lds, ldsA, fa, op.tab, blob, L);
                     break;
-                case 5: tile_block<R, 64, L>(lds, ldsA, fa, op, blob, L); break;
-                case 6: tile_block<R, 128, L>(lds, ldsA, fa, op, blob, L); break;
+                case 5: tile_block<R, 64, L>(lds, ldsA, fa, op.tab, blob, L); break;
+                case 6: tile_block<R, 128, L>(lds, ldsA, fa, op.tab, blob, L); break;
                 default: break;
             }
             __syncthreads();

@@ -26,8 +26,9 @@ enum : int32_t {
 // Block flags (TOp::flags of a TOP_BLOCK).
 enum : int32_t {
     BLK_RUN = 1,            // the next op is a DRUN_EPILOGUE run this block applies to its outputs
-    BLK_NOSYNC = 2          // each wave touches exactly the tile elements it touched in the
+    BLK_NOSYNC = 2,         // each wave touches exactly the tile elements it touched in the
                             // block before (same wave bits): no workgroup barrier between them
+    BLK_RUN_SIGNS = 4       // with BLK_RUN: the run is a sign run (DRUN_SIGNS)
 };
 
 struct TOp {
@@ -39,7 +40,9 @@ struct TOp {
     int32_t flags;          // diagonal run: DRUN_* bits
     uint64_t tab;           // block: byte offset of its address table (BlockTab layout);
                             // angle-path diagonal run: byte offset of its group offsets
+    uint64_t next_data;     // data of the pass's next TOP_BLOCK op (its fragments), 0 if none
 };
+static_assert(sizeof(TOp) == 64, "TOp is read as one 64-byte scalar load");
 
 // LDS slot of tile element e: the four low bits are XOR-ed with a fixed
 // image of every bit above them (bits 4..12 contribute 3, 5, 6, 9, 10, 12,
