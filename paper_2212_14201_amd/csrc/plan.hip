@@ -715,6 +715,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
     P->unit_of.assign(ng, -1);
     int32_t exec_counter = 0, unit_counter = 0;
     Builder B(P->blob);
+    size_t cis_off = 0;                  // the plan's cis table (put once, when a pass needs it)
     std::vector<int> pos(n), at(n);      // wire -> physical bit, physical bit -> wire
     std::iota(pos.begin(), pos.end(), 0);
     std::iota(at.begin(), at.end(), 0);
@@ -1019,8 +1020,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             }
         }
         // ---- block address tables and epilogue runs over the final layouts
+        bool epi_phases = false;               // a phase run rides in a block epilogue
         for (auto& er : epi_runs) {
             TOp& o = ops[er.first];
+            epi_phases = epi_phases || !(o.flags & DRUN_SIGNS);
             const TOp& blk = ops[er.first - 1];
             int8_t bitmap[32];
             epilogue_bitmap(blk.lb, blk.k, col_map(blk.lb, blk.k, L, dt, wsel[er.first - 1]), bitmap);
@@ -1059,6 +1062,17 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             return fail_plan(QVM_EARG, "internal: pass block width mismatch");
         pd.qmask = qmask;
         pd.ops = ops.empty() ? 0 : B.put(ops.data(), ops.size() * sizeof(TOp));
+        if (epi_phases && image) {
+            if (!cis_off) {
+                std::vector<float> t(2 * kCisEntries);
+                for (int j = 0; j < kCisEntries; ++j) {
+                    t[2 * j] = (float)std::cos(2.0 * M_PI * j / kCisEntries);
+                    t[2 * j + 1] = (float)std::sin(2.0 * M_PI * j / kCisEntries);
+                }
+                cis_off = B.put(t.data(), t.size() * sizeof(float));
+            }
+            pd.cistab = cis_off;
+        }
         std::vector<uint64_t> ldoff((size_t)1 << (L - c));
         for (size_t ch = 0; ch < ldoff.size(); ++ch) {
             uint64_t off = 0;

@@ -190,6 +190,21 @@ __device__ __forceinline__ void lds_st(uint32_t off, T v) {
     *(__attribute__((address_space(3))) T*)(size_t)off = v;
 }
 
+// exp(2 pi i a / 2^32) from the LDS cis table (at byte address tab): the
+// entry of the top kCisBits bits times cos + i sin of the rest, an angle
+// d below 2 pi / kCisEntries (cos d = 1 - d^2 / 2 and sin d = d - d^3 / 6
+// leave errors below d^4 / 24 < 6e-11).
+__device__ __forceinline__ void cis_lds(uint32_t a, uint32_t tab, float& c, float& s) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 t = lds_ld<f2>(tab + 8u * (a >> (32 - kCisBits)));
+    const float d = (float)(a & ((1u << (32 - kCisBits)) - 1u)) * 1.4629180792671596e-9f;   // 2 pi / 2^32
+    const float d2 = d * d;
+    const float cd = 1.f - 0.5f * d2;
+    const float sd = d - d * d2 * (1.f / 6);
+    c = t.x * cd - t.y * sd;
+    s = t.y * cd + t.x * sd;
+}
+
 // N uniform table words in one scalar load (dword alignment only).
 template <int N>
 __device__ __forceinline__ void sload(uint32_t (&dst)[N], const uint32_t* __restrict__ p) {
@@ -287,7 +302,8 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 template <typename R, int K, int LT, int RUN = 0, bool GA = false, int NF = 1>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NF],
                                            uint64_t tab_off, const char* __restrict__ blob, int L_,
-                                           const TOp* __restrict__ run = nullptr, int wave_ = -1) {
+                                           const TOp* __restrict__ run = nullptr, int wave_ = -1,
+                                           uint32_t cis_tab = 0) {
     static_assert(RUN == 0 || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
     constexpr int L = LT;                      // the kernel's tile width
@@ -446,7 +462,7 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
                             yi = __uint_as_float(__float_as_uint(yi) ^ f);
                         } else if constexpr (RUN == 1) {
                             R fr, fi;
-                            cis_turns(ang[ec % NEC], fr, fi);
+                            cis_lds(ang[ec % NEC], cis_tab, fr, fi);
                             const R xr = yr;
                             yr = fr * xr - fi * yi;
                             yi = fr * yi + fi * xr;
@@ -596,7 +612,8 @@ __device__ __forceinline__ void fetch_frag(R (&dst)[NF], uint64_t data, const ch
 // except before blocks marked BLK_NOSYNC.
 template <typename R, int L, int NF>
 __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp* __restrict__ ops, const PassDesc& pd,
-                                                 const char* __restrict__ blob, uint64_t base, R (&fa)[NF]) {
+                                                 const char* __restrict__ blob, uint64_t base, R (&fa)[NF],
+                                                 uint32_t cis_tab) {
     R fb[NF];
     bool first = true;           // the barrier after the load phase covers the first op
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -623,11 +640,11 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
             const TOp* run = &ops[oi + 1];
             if (NF == 4 || k == 3) {
                 if (erun == 2) tile_block<R, 16, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
-                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave, cis_tab);
                 else tile_block<R, 16, L, 0, true>(lds, lds, fa, tab, blob, L, nullptr, wave);
             } else if constexpr (NF >= 16) {
                 if (erun == 2) tile_block<R, 32, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
-                else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave);
+                else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave, cis_tab);
                 else tile_block<R, 32, L, 0, true>(lds, lds, fa, tab, blob, L, nullptr, wave);
             }
             if (has_next) {
@@ -707,6 +724,18 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     // the thread's piece offsets: its table entry plus the uniform one of i
     tofs += base;
 
+    // the cis table of phase runs in block epilogues, in LDS after the
+    // tile (and after the fragment area of passes with wider blocks)
+    const uint32_t cis_tab = (uint32_t)((2u << L) * sizeof(R)) +
+                             (MODE == 0 && pd.kmax >= 5 ? (uint32_t)((2u << pd.kmax) * (2u << pd.kmax) * sizeof(R)) : 0u);
+    if constexpr (sizeof(R) == 4 && L == 13) {
+        if (pd.cistab) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            static_assert(kCisEntries == 2 * NT, "one 16-byte piece of the table per thread");
+            const f4 v = *(const f4*)(blob + pd.cistab + 16 * threadIdx.x);
+            lds_st<f4>(cis_tab + 16 * threadIdx.x, v);
+        }
+    }
     // load: per batch, all loads in flight, then LDS.  The slot of piece i
     // is the thread's slot XOR a constant (the swizzle is linear and the
     // thread's bits and i's are disjoint).
@@ -728,7 +757,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
     __syncthreads();
 
     if constexpr (MODE > 0) {
-        tile_ops_regfrag<R, L, MODE>(lds, ops, pd, blob, base, fa);
+        tile_ops_regfrag<R, L, MODE>(lds, ops, pd, blob, base, fa, cis_tab);
     } else {
     // fragments: the first block's are copied to LDS with the tile (the
     // barrier below covers them); each later block's are read into
@@ -766,14 +795,14 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
                 case 3:
                     if constexpr (sizeof(R) == 4 && L == 13) {
                         if (erun == 2) { tile_block<R, 16, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op.tab, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op.tab, blob, L, run, -1, cis_tab); break; }
                     }
                     tile_block<R, 16, L>(lds, ldsA, fa, op.tab, blob, L);
                     break;
                 case 4:
                     if constexpr (sizeof(R) == 4 && L == 13) {
                         if (erun == 2) { tile_block<R, 32, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op.tab, blob, L, run); break; }
+                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op.tab, blob, L, run, -1, cis_tab); break; }
                     }
                     tile_block<R, 32, L>(lds, ldsA, fa, op.tab, blob, L);
                     break;
@@ -865,11 +894,11 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 || (MODE == 4 && L <= 12)) ? 4 
     tile_pass<R, L, MODE>(psi, pd, blob);
 }
 
-size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block) {
+size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block, bool cis) {
     const size_t es = dt == QVM_C64 ? 4 : 8;          // bytes per real
     // blocks of up to 4 qubits keep their fragments in registers
     const size_t K = kmax_block >= 5 ? (size_t)2 << kmax_block : 0;
-    return ((size_t)2 << L) * es + K * K * es;
+    return ((size_t)2 << L) * es + K * K * es + (cis ? (size_t)kCisEntries * 2 * sizeof(float) : 0);
 }
 
 template <typename R>
@@ -908,7 +937,8 @@ static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob
 }
 
 qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, double flops) {
-    const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax);
+    if (pd.cistab && (sv->dt != QVM_C64 || pd.L != 13)) return fail(QVM_EARG, "internal: cis table outside complex64 13-qubit passes");
+    const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax, pd.cistab != 0);
     if (lds > kTileLdsMax) return fail(QVM_EUNSUPPORTED, "pass needs more LDS than a workgroup has");
     return sv->dt == QVM_C64 ? launch_tile_t<float>(sv, pd, blob_dev, lds, flops)
                              : launch_tile_t<double>(sv, pd, blob_dev, lds, flops);

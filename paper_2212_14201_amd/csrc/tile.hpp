@@ -176,6 +176,15 @@ struct PassDesc {
     uint64_t ldoff;         // byte offset of uint64 off[2^(L-c)]: chunk -> physical offset
     uint64_t rmhi;          // byte offset of uint32 tab[2^(L-c)]: LDS slot of the remapped high local bits
     uint64_t rmlo;          // byte offset of uint32 tab[2^c]: LDS slot of the remapped low local bits
+    uint64_t cistab;        // complex64 passes with a phase run in a block epilogue: byte offset
+                            // of the cis table (kCisEntries float pairs), else 0
 };
+
+// The cis table of complex64 phase runs in block epilogues: entry j is
+// (cos, sin) of 2 pi j / kCisEntries, rounded to float; the kernel keeps it
+// in LDS after the tile and multiplies an entry by the short Taylor factor
+// of the remaining angle (below 2 pi / kCisEntries).
+constexpr int kCisBits = 10;
+constexpr int kCisEntries = 1 << kCisBits;
 
 }  // namespace qvm
