@@ -1037,14 +1037,21 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             o.data = B.put(et.data(), et.size() * sizeof(ETerm));
             o.tab = B.put(eoff.data(), eoff.size() * sizeof(uint32_t));
         }
-        if (image)
-            for (size_t oi = 0; oi < ops.size(); ++oi) {
-                TOp& o = ops[oi];
-                if (o.type != TOP_BLOCK) continue;
-                const std::vector<uint32_t> tab = block_table(o.lb, o.k, L, dt, col_map(o.lb, o.k, L, dt, wsel[oi]));
-                o.tab = B.put(tab.data(), tab.size() * sizeof(uint32_t));
-            }
         PassDesc pd{};
+        if (image && !ops.empty()) {
+            // every op's table slot, by op index (zeros for diagonal runs)
+            std::vector<uint32_t> tabs(ops.size() * kTabWords, 0u);
+            for (size_t oi = 0; oi < ops.size(); ++oi) {
+                if (ops[oi].type != TOP_BLOCK) continue;
+                const TOp& o = ops[oi];
+                const std::vector<uint32_t> tab = block_table(o.lb, o.k, L, dt, col_map(o.lb, o.k, L, dt, wsel[oi]));
+                if (tab.size() > (size_t)kTabWords) return fail_plan(QVM_EARG, "internal: block table too long");
+                std::copy(tab.begin(), tab.end(), tabs.begin() + oi * kTabWords);
+            }
+            pd.tabs = B.put(tabs.data(), tabs.size() * sizeof(uint32_t));
+            for (size_t oi = 0; oi < ops.size(); ++oi)
+                if (ops[oi].type == TOP_BLOCK) ops[oi].tab = pd.tabs + oi * kTabStride;
+        }
         pd.L = L;
         pd.c = c;
         pd.nops = (int)ops.size();

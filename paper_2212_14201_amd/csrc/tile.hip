@@ -299,11 +299,11 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // With GA (blocks of up to 4 qubits in passes without wider blocks) the A
 // fragments come from the caller's registers (fetched from the plan one
 // block ahead) instead of the LDS fragment area.
-template <typename R, int K, int LT, int RUN = 0, bool GA = false, int NF = 1>
+template <typename R, int K, int LT, int RUN = 0, bool GA = false, int NF = 1, bool PRE = false>
 __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restrict__ ldsA, const R (&fa)[NF],
                                            uint64_t tab_off, const char* __restrict__ blob, int L_,
                                            const TOp* __restrict__ run = nullptr, int wave_ = -1,
-                                           uint32_t cis_tab = 0) {
+                                           uint32_t cis_tab = 0, const uint32_t* pre = nullptr) {
     static_assert(RUN == 0 || (sizeof(R) == 4 && LT == 13 && (K == 16 || K == 32)),
                   "epilogue runs: complex64, 13-qubit tiles, k = 3, 4");
     constexpr int L = LT;                      // the kernel's tile width
@@ -341,16 +341,32 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
     // one column iteration per wave: its column tiles' words are loaded with
     // the others, so the block waits for its table once
     constexpr bool ONE = FULL && ntile == NW * CT;
-    uint32_t cw1[CT];
-    if constexpr (ONE) sload<CT>(cw1, tab + lay.col() + wave * CT);
-    // the block's uniform words that do not depend on the column tile,
-    // each group in one scalar load
+    static_assert(!PRE || ONE, "preloaded words: one column iteration per wave");
     constexpr int NBW = KS / 2, NEW = 4 * RB;
+    uint32_t cw1[CT];
     uint32_t lanew[4], rbit[4], bw[NBW], ew[NEW];
-    sload<4>(lanew, tab + lay.lane());
-    sload<4>(rbit, tab + lay.rbit());
-    sload<NBW>(bw, tab + lay.brow());
-    sload<NEW>(ew, tab + lay.erow());
+    if constexpr (PRE) {
+        // loaded by the caller with the op's record: the wave's column
+        // words, then the k-step, output-row, lane and row-bit words
+#pragma unroll
+        for (int i = 0; i < CT; ++i) cw1[i] = pre[i];
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) bw[i] = pre[CT + i];
+#pragma unroll
+        for (int i = 0; i < NEW; ++i) ew[i] = pre[CT + NBW + i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lanew[i] = pre[CT + NBW + NEW + i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rbit[i] = pre[CT + NBW + NEW + 4 + i];
+    } else {
+        if constexpr (ONE) sload<CT>(cw1, tab + lay.col() + wave * CT);
+        // the block's uniform words that do not depend on the column tile,
+        // each group in one scalar load
+        sload<4>(lanew, tab + lay.lane());
+        sload<4>(rbit, tab + lay.rbit());
+        sload<NBW>(bw, tab + lay.brow());
+        sload<NEW>(ew, tab + lay.erow());
+    }
     // lane-bit masks (all ones where bit i of the lane index is set): each
     // conditional slot below is one AND-XOR of a mask and a table word
     auto lmask = [&](int i) { return 0u - (((uint32_t)lane >> i) & 1u); };
@@ -617,10 +633,28 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
     R fb[NF];
     bool first = true;           // the barrier after the load phase covers the first op
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // 3-qubit block layout: column tiles, per-wave share (one iteration)
+    constexpr int CT3 = block_ct(3, L, sizeof(R) == 8);
+    constexpr int NTILE3 = L > 3 ? ((1 << (L - 3)) + 15) >> 4 : 1;
+    constexpr bool PRE3 = NF == 4 && L > 7 && NTILE3 == (NT / 64) * CT3 && (1 << (L - 3)) % 16 == 0;
+    static_assert(!PRE3 || 2 + 4 + 8 == 14, "3-qubit table words after the column words");
     for (int oi = 0; oi < pd.nops; ++oi) {
-        // the whole op record in one scalar load (one wait per op)
+        // the whole op record in one scalar load (one wait per op); in
+        // passes of 3-qubit blocks with one column iteration per wave, the
+        // op's table words too (they sit at a fixed stride by op index)
         uint32_t r[16];
         sload<16>(r, (const uint32_t*)(ops + oi));
+        uint32_t pw[PRE3 ? CT3 + 14 : 1];
+        if constexpr (PRE3) {
+            const uint32_t* __restrict__ tp = (const uint32_t*)(blob + pd.tabs) + oi * kTabWords;
+            uint32_t pc[CT3], ps[14];
+            sload<CT3>(pc, tp + wave * CT3);
+            sload<14>(ps, tp + NTILE3);
+#pragma unroll
+            for (int i = 0; i < CT3; ++i) pw[i] = pc[i];
+#pragma unroll
+            for (int i = 0; i < 14; ++i) pw[CT3 + i] = ps[i];
+        }
         const int32_t type = (int32_t)r[0], k = (int32_t)r[1], flags = (int32_t)r[11];
         const uint64_t data = r[8] | (uint64_t)r[9] << 32, tab = r[12] | (uint64_t)r[13] << 32;
         const uint64_t next_data = r[14] | (uint64_t)r[15] << 32;
@@ -639,9 +673,10 @@ __device__ __forceinline__ void tile_ops_regfrag(R* __restrict__ lds, const TOp*
             const int erun = !RUNOK || !(flags & BLK_RUN) ? 0 : (flags & BLK_RUN_SIGNS) ? 2 : 1;
             const TOp* run = &ops[oi + 1];
             if (NF == 4 || k == 3) {
-                if (erun == 2) tile_block<R, 16, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
-                else if (erun == 1) tile_block<R, 16, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave, cis_tab);
-                else tile_block<R, 16, L, 0, true>(lds, lds, fa, tab, blob, L, nullptr, wave);
+                if (erun == 2) tile_block<R, 16, L, RS, true, NF, PRE3>(lds, lds, fa, tab, blob, L, run, wave, 0, pw);
+                else if (erun == 1)
+                    tile_block<R, 16, L, RP, true, NF, PRE3>(lds, lds, fa, tab, blob, L, run, wave, cis_tab, pw);
+                else tile_block<R, 16, L, 0, true, NF, PRE3>(lds, lds, fa, tab, blob, L, nullptr, wave, 0, pw);
             } else if constexpr (NF >= 16) {
                 if (erun == 2) tile_block<R, 32, L, RS, true>(lds, lds, fa, tab, blob, L, run, wave);
                 else if (erun == 1) tile_block<R, 32, L, RP, true>(lds, lds, fa, tab, blob, L, run, wave, cis_tab);

@@ -94,6 +94,12 @@ struct BlockTabLayout {
     __host__ __device__ int words() const { return ntile + nb + ne + 8; }
 };
 
+// The address tables of a pass's block ops sit at a fixed stride by op
+// index (a table has at most 80 words: 13-qubit tiles, 3-qubit blocks), so
+// the kernel can load an op's table together with its record.
+constexpr int kTabWords = 80;
+constexpr size_t kTabStride = kTabWords * sizeof(uint32_t);
+
 // Column tiles a wave takes per iteration in the block kernel (K = 2^(k+1)
 // real rows): complex64 8 for k = 3, 4 for k = 4; complex128 4 / (K / 16);
 // 1 for k >= 5; at most the wave's share of the tile's column tiles.
@@ -176,6 +182,7 @@ struct PassDesc {
     uint64_t ldoff;         // byte offset of uint64 off[2^(L-c)]: chunk -> physical offset
     uint64_t rmhi;          // byte offset of uint32 tab[2^(L-c)]: LDS slot of the remapped high local bits
     uint64_t rmlo;          // byte offset of uint32 tab[2^c]: LDS slot of the remapped low local bits
+    uint64_t tabs;          // byte offset of the ops' address tables: op i's at tabs + i kTabStride
     uint64_t cistab;        // complex64 passes with a phase run in a block epilogue: byte offset
                             // of the cis table (kCisEntries float pairs), else 0
 };

@@ -40,7 +40,7 @@ def header_functions():
 # Device-image records of the tile kernel (layouts in csrc/tile.hpp).
 _PD = np.dtype([("L", "<i4"), ("c", "<i4"), ("nops", "<i4"), ("remap", "<i4"), ("kmax", "<i4"),
                 ("first_block", "<i4"), ("qmask", "<u8"), ("ops", "<u8"), ("ldoff", "<u8"),
-                ("rmhi", "<u8"), ("rmlo", "<u8"), ("cistab", "<u8")])
+                ("rmhi", "<u8"), ("rmlo", "<u8"), ("tabs", "<u8"), ("cistab", "<u8")])
 _TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"),
                  ("next_block", "<i4"), ("flags", "<i4"), ("tab", "<u8"), ("next_data", "<u8")])
 _DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
