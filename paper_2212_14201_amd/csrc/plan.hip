@@ -821,6 +821,10 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             }
             ++unit_counter;
         };
+        // widest block of the pass (blocks are padded to 3 qubits)
+        int kmax_pass = 0;
+        for (const auto& u : pp.units)
+            if (u.block) kmax_pass = std::max(kmax_pass, std::max(3, (int)u.qubits.size()));
         auto flush = [&]() {
             for (const Unit* h : held) place(*h);
             held.clear();
@@ -834,7 +838,9 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             for (const DSub& d : run) signs = signs && d.neg;
             const int at_least = signs ? kTurnsMinSignTerms : kTurnsMinTerms;
             int8_t bitmap[32];
-            const bool fuse_prev = !ops.empty() && ops.back().type == TOP_BLOCK &&
+            // (passes with blocks of 5 or more qubits stage fragments in LDS and
+            // apply every run on its own)
+            const bool fuse_prev = !ops.empty() && ops.back().type == TOP_BLOCK && kmax_pass <= 4 &&
                                    !(ops.back().flags & BLK_RUN) && epilogue_ok(ops.back().k, L, dt);
             if (fuse_prev) {
                 // applied in the block's epilogue (no pass of its own); the
@@ -871,10 +877,6 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             }
             ops.push_back(op);
         };
-        // widest block of the pass (blocks are padded to 3 qubits)
-        int kmax_pass = 0;
-        for (const auto& u : pp.units)
-            if (u.block) kmax_pass = std::max(kmax_pass, std::max(3, (int)u.qubits.size()));
         for (auto& u : pp.units) {
             TOp op{};
             if (u.block) {
@@ -1020,6 +1022,8 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             }
         }
         // ---- block address tables and epilogue runs over the final layouts
+        if (kmax_pass >= 5 && !epi_runs.empty())
+            return fail_plan(QVM_EARG, "internal: epilogue run in a pass of 5- or 6-qubit blocks");
         bool epi_phases = false;               // a phase run rides in a block epilogue
         for (auto& er : epi_runs) {
             TOp& o = ops[er.first];

@@ -65,6 +65,13 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 
 __device__ __forceinline__ uint32_t sw(uint32_t e) { return tile_swizzle(e); }
 
+// Slot of element a + b for a < 2^m and b a multiple of 2^m (m >= 4): the
+// swizzle only changes bits 0..3, so sw(a + b) = (sw(a) ^ low) + b with low
+// = sw(b) ^ b below 16.  For a constant b the XOR takes an inline constant
+// and the add folds into the LDS instruction's offset (no register holds
+// the constant).
+__device__ __forceinline__ uint32_t sw_add(uint32_t swa, uint32_t b) { return (swa ^ (sw(b) ^ b)) + b; }
+
 // A 16-byte piece of two complex64 elements (2m, 2m + 1) as it sits in LDS:
 // at the slot pair of sw(2m), swapped when that slot is odd (the swizzle
 // keeps the pair adjacent but may reverse it).  Its own inverse.
@@ -525,7 +532,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
         if (live) {
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
-                const uint32_t s = 2 * (swt ^ sw(NT * (uint32_t)(i0 + i)));
+                const uint32_t s = 2 * sw_add(swt, NT * (uint32_t)(i0 + i));
                 xr[i] = lds[s];
                 xi[i] = lds[s + 1];
             }
@@ -563,7 +570,7 @@ __device__ __forceinline__ void tile_diagrun(R* __restrict__ lds, const DSub* __
         if (live) {
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
-                const uint32_t s = 2 * (swt ^ sw(NT * (uint32_t)(i0 + i)));
+                const uint32_t s = 2 * sw_add(swt, NT * (uint32_t)(i0 + i));
                 lds[s] = xr[i];
                 lds[s + 1] = xi[i];
             }
@@ -586,7 +593,7 @@ __device__ __forceinline__ void tile_diagrun_turns(R* __restrict__ lds, const DT
     const uint32_t swt = sw(t);
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        const uint32_t e = 2 * (swt ^ sw(NT * (uint32_t)i));
+        const uint32_t e = 2 * sw_add(swt, NT * (uint32_t)i);
         const R xr = lds[e], xi = lds[e + 1];
         if (signs) {
             // the accumulated angle is 0 or a half turn
@@ -784,7 +791,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
                 v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * (tofs + ldoff[HI * (b0 + it)])));
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
-                const uint32_t s = se0 ^ sw((uint32_t)EP * NT * (uint32_t)(b0 + it));
+                const uint32_t s = sw_add(se0, (uint32_t)EP * NT * (uint32_t)(b0 + it));
                 *(V16*)(lds + 2 * (s & ~(uint32_t)(EP - 1))) = pair_order<EP>(v[it], s);
             }
         }
@@ -823,24 +830,10 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
                     }
                 }
             }
-            // a diagonal run right after the block may ride in its epilogue
-            const int erun = !(op.flags & BLK_RUN) ? 0 : (ops[oi + 1].flags & DRUN_SIGNS) ? 2 : 1;
-            const TOp* run = &ops[oi + 1];
+            // (the planner puts no run in the epilogue of a block in these passes)
             switch (op.k) {
-                case 3:
-                    if constexpr (sizeof(R) == 4 && L == 13) {
-                        if (erun == 2) { tile_block<R, 16, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 16, L, 1>(lds, ldsA, fa, op.tab, blob, L, run, -1, cis_tab); break; }
-                    }
-                    tile_block<R, 16, L>(lds, ldsA, fa, op.tab, blob, L);
-                    break;
-                case 4:
-                    if constexpr (sizeof(R) == 4 && L == 13) {
-                        if (erun == 2) { tile_block<R, 32, L, 2>(lds, ldsA, fa, op.tab, blob, L, run); break; }
-                        if (erun == 1) { tile_block<R, 32, L, 1>(lds, ldsA, fa, op.tab, blob, L, run, -1, cis_tab); break; }
-                    }
-                    tile_block<R, 32, L>(lds, ldsA, fa, op.tab, blob, L);
-                    break;
+                case 3: tile_block<R, 16, L>(lds, ldsA, fa, op.tab, blob, L); break;
+                case 4: tile_block<R, 32, L>(lds, ldsA, fa, op.tab, blob, L); break;
                 case 5: tile_block<R, 64, L>(lds, ldsA, fa, op.tab, blob, L); break;
                 case 6: tile_block<R, 128, L>(lds, ldsA, fa, op.tab, blob, L); break;
                 default: break;
@@ -896,7 +889,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
             if (!remap) {
 #pragma unroll
                 for (int it = 0; it < BATCH; ++it) {
-                    const uint32_t s = ss0 ^ sw((uint32_t)EP * NT * (uint32_t)(b0 + it));
+                    const uint32_t s = sw_add(ss0, (uint32_t)EP * NT * (uint32_t)(b0 + it));
                     v[it] = pair_order<EP>(*(const V16*)(lds + 2 * (s & ~(uint32_t)(EP - 1))), s);
                 }
             } else {

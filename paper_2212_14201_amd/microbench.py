@@ -27,6 +27,8 @@ def main():
     ap.add_argument("--k", type=int, default=4, help="blocks: block width in qubits")
     ap.add_argument("--blocks", type=int, default=32, help="blocks: fused blocks in the one tile pass")
     ap.add_argument("--tile", type=int, default=13, help="blocks: tile qubits of the pass")
+    ap.add_argument("--classic", action="store_true",
+                    help="tile: the classic plan (one 5-qubit block per pass) instead of 3-qubit blocks in tiles")
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--launches", type=int, default=3)
@@ -129,7 +131,8 @@ def main():
     else:
         cfg = config_circuit("qft30") if a.n == 30 else None
         gates = cfg["gates"] if cfg else [Gate("h", (q,)) for q in range(a.n)]
-        plan = qvm.Plan(gates, a.n, a.dtype, k_max=3, tile_qubits=13 if a.dtype == "c64" else 12)
+        plan = (qvm.Plan(gates, a.n, a.dtype, k_max=5, tile_qubits=0) if a.classic
+                else qvm.Plan(gates, a.n, a.dtype, k_max=3, tile_qubits=13 if a.dtype == "c64" else 12))
         for _ in range(a.launches):
             sv.init_basis(0)
             plan.run(sv)
