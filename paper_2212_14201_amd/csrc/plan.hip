@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -430,6 +431,69 @@ void epilogue_terms(const std::vector<DTerm>& terms, const std::vector<uint32_t>
     }
 }
 
+// Phase sums of the phase runs a pass applies in block epilogues (layout
+// in tile.hpp), built run by run: a run's terms by group and thread
+// condition (combos, in order of first appearance), records with equal
+// tile-index tests merged and zero sums dropped, each thread condition as
+// one lane mask per wave (thread t = 64 wave + lane), every group's combos
+// padded to a multiple of 4.
+struct PSumBuild {
+    std::vector<uint32_t> cb{0};
+    std::vector<PRec> recs;
+    std::vector<std::array<uint64_t, kTileThreads / 64>> masks;   // per wave
+};
+
+void epilogue_psums(const std::vector<DTerm>& terms, const std::vector<uint32_t>& off, uint64_t qmask,
+                    PSumBuild& ps, std::vector<uint32_t>& goff) {
+    goff.assign(17, (uint32_t)ps.masks.size());
+    for (uint32_t g = 0; g < 16; ++g) {
+        std::vector<std::pair<uint64_t, std::vector<PRec>>> combos;
+        for (uint32_t q = off[g]; q < off[g + 1]; ++q) {
+            const DTerm& d = terms[q];
+            const uint64_t key = (uint64_t)d.lmask << 32 | d.lval;
+            auto c = std::find_if(combos.begin(), combos.end(), [&](const auto& x) { return x.first == key; });
+            if (c == combos.end()) c = combos.insert(combos.end(), std::make_pair(key, std::vector<PRec>{}));
+            const PRec r{outer_bits(d.omask, qmask), outer_bits(d.oval, qmask), (uint32_t)d.turns, 0};
+            auto same = std::find_if(c->second.begin(), c->second.end(),
+                                     [&](const PRec& e) { return e.om == r.om && e.ov == r.ov; });
+            if (same != c->second.end()) same->w += r.w;
+            else c->second.push_back(r);
+        }
+        for (auto& c : combos) {
+            size_t kept = 0;
+            for (const PRec& r : c.second)
+                if (r.w) {
+                    ps.recs.push_back(r);
+                    ++kept;
+                }
+            if (!kept) continue;
+            const uint32_t lm = (uint32_t)(c.first >> 32), lv = (uint32_t)c.first;
+            std::array<uint64_t, kTileThreads / 64> m{};
+            for (uint32_t w = 0; w < kTileThreads / 64; ++w)
+                for (uint32_t lane = 0; lane < 64; ++lane)
+                    if (((64 * w + lane) & lm) == lv) m[w] |= 1ull << lane;
+            ps.cb.push_back((uint32_t)ps.recs.size());
+            ps.masks.push_back(m);
+        }
+        while ((ps.masks.size() - goff[g]) % 4) {
+            ps.cb.push_back((uint32_t)ps.recs.size());
+            ps.masks.push_back({});
+        }
+        goff[g + 1] = (uint32_t)ps.masks.size();
+    }
+}
+
+// Upper bound on the combos a phase run adds to its pass's phase sums,
+// whatever block layout it ends up on: a condition h = 0 on an element bit
+// splits a term in two (at most four element bits), and each group's
+// combos are padded to a multiple of 4.
+int psum_bound(const std::vector<DSub>& run, int L) {
+    const uint64_t tile = L >= 64 ? ~0ull : (1ull << L) - 1;
+    int n = 16 * 3;
+    for (const DSub& d : run) n += 1 << std::min(4, __builtin_popcountll(d.lmask & ~d.lval & tile));
+    return n;
+}
+
 // The standalone run's element layout: thread t holds elements
 // t + kTileThreads i, so tile bits below kLogTileThreads are thread bits and
 // the ones above are element bits.
@@ -808,6 +872,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         // runs that ride in a block's epilogue: encoded once the block's
         // column layout is fixed (after the wave bits are chosen)
         std::vector<std::pair<size_t, std::vector<DSub>>> epi_runs;
+        int psum_combos = 0;          // bound on the phase sums' combos so far
         // Diagonal gates commute with each other and with blocks on other
         // wires, so they are held back until a block touches one of their
         // wires (or the pass ends) and then emitted as one run: fewer, longer
@@ -840,8 +905,11 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             int8_t bitmap[32];
             // (passes with blocks of 5 or more qubits stage fragments in LDS and
             // apply every run on its own)
+            // (a phase run's sums share a bounded LDS area with the pass's others)
+            const int need = signs ? 0 : psum_bound(run, L);
             const bool fuse_prev = !ops.empty() && ops.back().type == TOP_BLOCK && kmax_pass <= 4 &&
-                                   !(ops.back().flags & BLK_RUN) && epilogue_ok(ops.back().k, L, dt);
+                                   !(ops.back().flags & BLK_RUN) && epilogue_ok(ops.back().k, L, dt) &&
+                                   psum_combos + need <= kPSumMax;
             if (fuse_prev) {
                 // applied in the block's epilogue (no pass of its own); the
                 // default layout tells whether the run's phases cancel
@@ -856,6 +924,7 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 op.k = (int32_t)terms.size();
                 op.flags = DRUN_TURNS | (signs ? DRUN_SIGNS : 0) | DRUN_EPILOGUE;
                 ops.back().flags |= BLK_RUN | (signs ? BLK_RUN_SIGNS : 0);
+                psum_combos += need;
                 epi_runs.emplace_back(ops.size(), std::move(run));
                 run.clear();
             } else if ((int)run.size() >= at_least) {
@@ -1024,22 +1093,51 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
         // ---- block address tables and epilogue runs over the final layouts
         if (kmax_pass >= 5 && !epi_runs.empty())
             return fail_plan(QVM_EARG, "internal: epilogue run in a pass of 5- or 6-qubit blocks");
-        bool epi_phases = false;               // a phase run rides in a block epilogue
+        PSumBuild ps;                          // phase runs in block epilogues
+        std::vector<size_t> phase_ops;
         for (auto& er : epi_runs) {
             TOp& o = ops[er.first];
-            epi_phases = epi_phases || !(o.flags & DRUN_SIGNS);
             const TOp& blk = ops[er.first - 1];
             int8_t bitmap[32];
             epilogue_bitmap(blk.lb, blk.k, col_map(blk.lb, blk.k, L, dt, wsel[er.first - 1]), bitmap);
             std::vector<DTerm> terms;
             std::vector<uint32_t> off;
             angle_terms(er.second, L, dt, bitmap, 4, terms, off);
-            std::vector<ETerm> et;
-            std::vector<uint32_t> eoff;
-            epilogue_terms(terms, off, qmask, (o.flags & DRUN_SIGNS) != 0, et, eoff);
             o.k = (int32_t)terms.size();
-            o.data = B.put(et.data(), et.size() * sizeof(ETerm));
-            o.tab = B.put(eoff.data(), eoff.size() * sizeof(uint32_t));
+            if (o.flags & DRUN_SIGNS) {
+                std::vector<ETerm> et;
+                std::vector<uint32_t> eoff;
+                epilogue_terms(terms, off, qmask, true, et, eoff);
+                o.data = B.put(et.data(), et.size() * sizeof(ETerm));
+                o.tab = B.put(eoff.data(), eoff.size() * sizeof(uint32_t));
+            } else {
+                std::vector<uint32_t> goff;
+                epilogue_psums(terms, off, qmask, ps, goff);
+                o.tab = B.put(goff.data(), goff.size() * sizeof(uint32_t));
+                phase_ops.push_back(er.first);
+            }
+        }
+        const bool epi_phases = !phase_ops.empty();
+        size_t psum_off = 0;
+        const uint32_t ncombo = (uint32_t)ps.masks.size();
+        if (epi_phases) {
+            if (ncombo > (uint32_t)kPSumMax || ncombo > (uint32_t)psum_combos)
+                return fail_plan(QVM_EARG, "internal: phase sums above their bound");
+            constexpr int NW = kTileThreads / 64;
+            PSumHead h{};
+            h.ncombo = ncombo;
+            h.nrec = (uint32_t)ps.recs.size();
+            h.rec_off = (uint32_t)((sizeof(PSumHead) + 4 * (ncombo + 1) + 15) & ~(size_t)15);
+            h.mask_off = h.rec_off + (uint32_t)(sizeof(PRec) * ps.recs.size());
+            std::vector<char> t(h.mask_off + sizeof(uint64_t) * NW * ncombo, 0);
+            memcpy(t.data(), &h, sizeof h);
+            memcpy(t.data() + sizeof h, ps.cb.data(), 4 * ps.cb.size());
+            if (!ps.recs.empty()) memcpy(t.data() + h.rec_off, ps.recs.data(), sizeof(PRec) * ps.recs.size());
+            uint64_t* m = (uint64_t*)(t.data() + h.mask_off);
+            for (uint32_t c = 0; c < ncombo; ++c)
+                for (int w = 0; w < NW; ++w) m[(size_t)w * ncombo + c] = ps.masks[c][w];
+            psum_off = B.put(t.data(), t.size());
+            for (size_t oi : phase_ops) ops[oi].data = psum_off;
         }
         PassDesc pd{};
         if (image && !ops.empty()) {
@@ -1083,6 +1181,8 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
                 cis_off = B.put(t.data(), t.size() * sizeof(float));
             }
             pd.cistab = cis_off;
+            pd.psum = psum_off;
+            pd.npsum = (int32_t)ncombo;
         }
         std::vector<uint64_t> ldoff((size_t)1 << (L - c));
         for (size_t ch = 0; ch < ldoff.size(); ++ch) {

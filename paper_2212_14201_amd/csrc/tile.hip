@@ -225,7 +225,7 @@ __device__ __forceinline__ void sload(uint32_t (&dst)[N], const uint32_t* __rest
     }
 }
 
-// Runs applied in a block's epilogue (ETerm records, complex64): whether a
+// Sign runs applied in a block's epilogue (ETerm records, complex64): whether a
 // record matches thread t of tile w, as a vector test (tile-index test and
 // thread test in one compare, no scalar compares); two records per scalar
 // load (groups are padded to even counts).
@@ -250,20 +250,38 @@ __device__ __forceinline__ uint32_t erun_signs(const ETerm* __restrict__ terms, 
     return m;
 }
 
-// A phase run: the thread's angle per element code (turns of 2^-32), one
-// sum per group, then subset sums over the four element-code bits.
-__device__ __forceinline__ void erun_angles(uint32_t (&acc)[16], const ETerm* __restrict__ terms,
-                                            const uint32_t* __restrict__ grp, uint32_t w, uint32_t t) {
+// A phase run from the pass's phase sums (layout in tile.hpp): per group,
+// the sum of each combo (formed by the workgroup before its first op, in
+// LDS at psum) where the thread meets the combo's thread condition (its
+// wave's lane mask), four combos per step; then subset sums over the four
+// element-code bits.
+__device__ __forceinline__ void erun_psums(uint32_t (&acc)[16], const char* __restrict__ tab,
+                                           const uint32_t* __restrict__ grp, int wave, uint32_t psum) {
+    typedef uint32_t U4 __attribute__((ext_vector_type(4)));
+    uint32_t hd[4];
+    sload<4>(hd, (const uint32_t*)tab);
+    const uint32_t* __restrict__ mk = (const uint32_t*)(tab + hd[3]) + 2 * (size_t)wave * hd[0];
+    uint32_t go[17];                   // the group offsets in two scalar loads, one wait
+    {
+        uint32_t g16[16], g1[1];
+        sload<16>(g16, grp);
+        sload<1>(g1, grp + 16);
+#pragma unroll
+        for (int g = 0; g < 16; ++g) go[g] = g16[g];
+        go[16] = g1[0];
+    }
 #pragma unroll
     for (int g = 0; g < 16; ++g) {
         uint32_t a = 0;
-        const uint32_t q1 = grp[g + 1];
+        const uint32_t c1 = go[g + 1];
 #pragma unroll 1
-        for (uint32_t q = grp[g]; q < q1; q += 2) {
-            uint32_t r[16];
-            sload<16>(r, (const uint32_t*)(terms + q));
-            a += eterm_on(r, w, t) ? r[4] : 0u;
-            a += eterm_on(r + 8, w, t) ? r[12] : 0u;
+        for (uint32_t c = go[g]; c < c1; c += 4) {
+            uint32_t m[8];
+            sload<8>(m, mk + 2 * c);
+            const U4 v = lds_ld<U4>(psum + 4 * c);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a += __builtin_amdgcn_inverse_ballot_w64(m[2 * j] | (uint64_t)m[2 * j + 1] << 32) ? v[j] : 0u;
         }
         acc[g] = a;
     }
@@ -296,8 +314,9 @@ constexpr int AREG_MAX = 32;       // widest real block (K = 2^(k+1)) whose frag
 // With RUN (complex64, 13-qubit tiles, 3- and 4-qubit blocks: one column
 // iteration per wave) the diagonal run that follows the block is applied to
 // the outputs before they are stored: RUN = 1 a run of phases (one factor
-// per element from its angle sum), RUN = 2 a run of sign flips (one parity
-// bit per element).  The run's terms are encoded over the
+// per element from its angle sum, from the pass's phase sums), RUN = 2 a
+// run of sign flips (one parity bit per element).  The run's terms are
+// encoded over the
 // epilogue's layout: thread code threadIdx.x (lane l holds column bits 0..3
 // as l % 16 and block bits 1, 2 as l / 16; the wave holds the top column
 // bits) and element code hh | ct << 1 | rb << (1 + log2 CT) (block bit 0,
@@ -459,9 +478,10 @@ __device__ __forceinline__ void tile_block(R* __restrict__ lds, const R* __restr
         // the tile index: a vector operand where registers allow (the run's
         // tile-index tests then take no scalar instructions)
         uint32_t wv = blockIdx.x;
-        if constexpr (RUN != 0 && GA && NF == 4) asm volatile("" : "+v"(wv));
+        if constexpr (RUN == 2 && GA && NF == 4) asm volatile("" : "+v"(wv));
         if constexpr (RUN == 1)
-            erun_angles(ang, (const ETerm*)(blob + run->data), (const uint32_t*)(blob + run->tab), wv, threadIdx.x);
+            erun_psums(ang, blob + run->data, (const uint32_t*)(blob + run->tab), wave,
+                       cis_tab + 8u * kCisEntries);
         // a sign run: the thread's flips, one bit per element code
         uint32_t smask = 0;
         if constexpr (RUN == 2)
@@ -778,6 +798,35 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
             lds_st<f4>(cis_tab + 16 * threadIdx.x, v);
         }
     }
+    // the phase sums of the pass's epilogue phase runs (after the cis
+    // table): the combos split over the waves, each summed on the scalar
+    // unit while the first batch of the tile's loads is in flight; the
+    // barrier after the load phase publishes them
+    auto phase_sums = [&]() {
+        if constexpr (sizeof(R) == 4 && L == 13) {
+            if (pd.psum) {
+                const uint32_t* __restrict__ tp = (const uint32_t*)(blob + pd.psum);
+                uint32_t hd[4];
+                sload<4>(hd, tp);
+                const uint32_t* __restrict__ rec = tp + hd[2] / 4;
+                const uint32_t w = blockIdx.x;
+                const uint32_t psum = cis_tab + 8u * kCisEntries;
+#pragma unroll 1
+                for (uint32_t c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); c < hd[0]; c += NT / 64) {
+                    uint32_t cr[2];
+                    sload<2>(cr, tp + 4 + c);
+                    uint32_t sum = 0;
+#pragma unroll 1
+                    for (uint32_t r = cr[0]; r < cr[1]; ++r) {
+                        uint32_t q[4];
+                        sload<4>(q, rec + 4 * r);
+                        sum += (w & q[0]) == q[1] ? q[2] : 0u;
+                    }
+                    if ((threadIdx.x & 63) == 0) lds_st<uint32_t>(psum + 4 * c, sum);
+                }
+            }
+        }
+    };
     // load: per batch, all loads in flight, then LDS.  The slot of piece i
     // is the thread's slot XOR a constant (the swizzle is linear and the
     // thread's bits and i's are disjoint).
@@ -789,6 +838,7 @@ __device__ __forceinline__ void tile_pass(R* __restrict__ psi, const PassDesc& p
 #pragma unroll
             for (int it = 0; it < BATCH; ++it)
                 v[it] = __builtin_nontemporal_load((const V16*)(psi + 2 * (tofs + ldoff[HI * (b0 + it)])));
+            if (b0 == 0) phase_sums();
 #pragma unroll
             for (int it = 0; it < BATCH; ++it) {
                 const uint32_t s = sw_add(se0, (uint32_t)EP * NT * (uint32_t)(b0 + it));
@@ -922,11 +972,12 @@ __global__ __launch_bounds__(NT, (sizeof(R) == 4 || (MODE == 4 && L <= 12)) ? 4 
     tile_pass<R, L, MODE>(psi, pd, blob);
 }
 
-size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block, bool cis) {
+size_t tile_lds_bytes(qvm_dtype dt, int L, int kmax_block, bool cis, int npsum) {
     const size_t es = dt == QVM_C64 ? 4 : 8;          // bytes per real
     // blocks of up to 4 qubits keep their fragments in registers
     const size_t K = kmax_block >= 5 ? (size_t)2 << kmax_block : 0;
-    return ((size_t)2 << L) * es + K * K * es + (cis ? (size_t)kCisEntries * 2 * sizeof(float) : 0);
+    return ((size_t)2 << L) * es + K * K * es +
+           (cis ? (size_t)kCisEntries * 2 * sizeof(float) + (size_t)4 * npsum : 0);
 }
 
 template <typename R>
@@ -966,7 +1017,9 @@ static qvm_status launch_tile_t(qvm_sv* sv, const PassDesc& pd, const char* blob
 
 qvm_status launch_tile_pass(qvm_sv* sv, const PassDesc& pd, const char* blob_dev, double flops) {
     if (pd.cistab && (sv->dt != QVM_C64 || pd.L != 13)) return fail(QVM_EARG, "internal: cis table outside complex64 13-qubit passes");
-    const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax, pd.cistab != 0);
+    if ((pd.psum != 0) != (pd.npsum > 0) || pd.npsum % 4 || pd.npsum > kPSumMax || (pd.psum && !pd.cistab))
+        return fail(QVM_EARG, "internal: phase sums of a pass");
+    const size_t lds = tile_lds_bytes(sv->dt, pd.L, pd.kmax, pd.cistab != 0, pd.npsum);
     if (lds > kTileLdsMax) return fail(QVM_EUNSUPPORTED, "pass needs more LDS than a workgroup has");
     return sv->dt == QVM_C64 ? launch_tile_t<float>(sv, pd, blob_dev, lds, flops)
                              : launch_tile_t<double>(sv, pd, blob_dev, lds, flops);

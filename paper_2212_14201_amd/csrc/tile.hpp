@@ -151,17 +151,17 @@ struct DTerm {
 };
 static_assert(sizeof(DTerm) == 32, "DTerm layout");
 
-// One term of a diagonal run applied in a block's epilogue (DRUN_EPILOGUE,
-// complex64): the DTerm condition with the tile's outer-bit test taken over
-// the workgroup index (the tile index, whose bits are the non-tile physical
-// bits in ascending order), so that every field is 32 bits.  A term matches
-// thread t of tile w when (w & om) == ov and (t & lm) == lv, and element code
-// i when i contains its group's element bits.  w holds the term's angle in
-// turns of 2^-32 for a phase run; for a sign run (every term a factor of
-// -1) the element codes it flips: the codes that contain its group.  The
-// records are stored by group with offsets (17 words, TOp::tab); each
-// group is padded to an even count with a record that never matches
-// (om = 0, ov = 1), as the kernel reads two records per scalar load.
+// One term of a sign run (every term a factor of -1) applied in a block's
+// epilogue (DRUN_EPILOGUE, complex64): the DTerm condition with the tile's
+// outer-bit test taken over the workgroup index (the tile index, whose bits
+// are the non-tile physical bits in ascending order), so that every field
+// is 32 bits.  A term matches thread t of tile w when (w & om) == ov and
+// (t & lm) == lv, and element code i when i contains its group's element
+// bits; w holds the element codes it flips: the codes that contain its
+// group.  The records are stored by group with offsets (17 words,
+// TOp::tab); each group is padded to an even count with a record that
+// never matches (om = 0, ov = 1), as the kernel reads two records per
+// scalar load.  (Phase runs in epilogues use the phase sums below.)
 struct ETerm {
     uint32_t om, ov;
     uint32_t lm, lv;
@@ -169,6 +169,38 @@ struct ETerm {
     uint32_t pad_[3];       // 32 bytes: two records per 64-byte scalar load
 };
 static_assert(sizeof(ETerm) == 32, "ETerm layout");
+
+// Phase runs in block epilogues (complex64) are encoded per pass as phase
+// sums instead of ETerm records.  A run's terms are merged into combos: the
+// terms of one group (element-code bits) with one thread condition
+// (t & lm) == lv.  A combo's sum S(w) = sum of its records' turns whose
+// tile-index test (w & om) == ov holds depends on the tile only, so each
+// workgroup forms every combo's S once, on the scalar unit, while its tile
+// loads are in flight (combos split over the waves), and keeps them in LDS
+// after the cis table.  In the epilogue a thread adds S of each combo of
+// a group whose thread condition it meets; that condition is stored as one
+// 64-bit lane mask per wave (thread t = 64 wave + lane), so a combo costs a
+// masked select and an add.
+//
+// The pass's table (PassDesc::psum): a PSumHead, then uint32 cb[ncombo + 1]
+// (combo c's records are [cb[c], cb[c + 1])), the records (PRec, at
+// rec_off) and the lane masks (uint64 mask[8][ncombo], at mask_off; byte
+// offsets from the table).  A run op's tab holds 17 words: its groups'
+// combo ranges (pass combo indices, each group's range a multiple of 4,
+// padded with combos without records); its data is the pass's table.
+struct PSumHead {
+    uint32_t ncombo;        // multiple of 4
+    uint32_t nrec;
+    uint32_t rec_off;       // 16-byte aligned
+    uint32_t mask_off;      // 16-byte aligned
+};
+struct PRec {
+    uint32_t om, ov;        // tile-index test
+    uint32_t w;             // turns of 2^-32
+    uint32_t pad_;
+};
+static_assert(sizeof(PSumHead) == 16 && sizeof(PRec) == 16, "phase-sum layout");
+constexpr int kPSumMax = 1024;     // combos per pass (4 KiB of LDS)
 
 struct PassDesc {
     int32_t L;              // tile qubits
@@ -185,6 +217,9 @@ struct PassDesc {
     uint64_t tabs;          // byte offset of the ops' address tables: op i's at tabs + i kTabStride
     uint64_t cistab;        // complex64 passes with a phase run in a block epilogue: byte offset
                             // of the cis table (kCisEntries float pairs), else 0
+    uint64_t psum;          // such passes: byte offset of the phase-sum table, else 0
+    int32_t npsum;          // its combo count (LDS words after the cis table)
+    int32_t pad_;
 };
 
 // The cis table of complex64 phase runs in block epilogues: entry j is

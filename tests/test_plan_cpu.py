@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import (_DSUB, _DTERM, _ETERM, _TOP, blocks_and_diagonals, plan_image,
+from tests.util import (_DSUB, _DTERM, _ETERM, _PREC, _TOP, blocks_and_diagonals, plan_image,
                         tile_blocks_outer_diagonals)
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit,
                        random_mixed_circuit, random_planner_circuit)
@@ -464,24 +464,49 @@ def deposit(w, qmask):
     return out
 
 
-def epilogue_factors(terms, off, w, signs):
-    """Factors of a run applied in a block's epilogue, per (element code,
-    thread code), for tile index w: records matched on the tile index and
-    the thread, sign runs as parities over the element codes each record
-    lists, phase runs as grouped angle sums and subset sums."""
+def epilogue_sign_factors(terms, off, w):
+    """Factors of a sign run applied in a block's epilogue, per (element
+    code, thread code), for tile index w: records matched on the tile index
+    and the thread, parities over the element codes each record lists."""
     t = np.arange(512, dtype=np.int64)
     assert off[-1] == len(terms) and np.all(np.diff(off.astype(np.int64)) % 2 == 0)
-    hit = lambda d: ((w & int(d["om"])) == int(d["ov"])) & ((t & int(d["lm"])) == int(d["lv"]))
-    if signs:
-        m = np.zeros(512, np.int64)
-        for d in terms:
-            m ^= np.where(hit(d), int(d["w"]), 0)
-        flips = (m[None, :] >> np.arange(16)[:, None]) & 1
-        return np.where(flips == 1, -1.0, 1.0)
+    m = np.zeros(512, np.int64)
+    for d in terms:
+        hit = ((w & int(d["om"])) == int(d["ov"])) & ((t & int(d["lm"])) == int(d["lv"]))
+        m ^= np.where(hit, int(d["w"]), 0)
+    flips = (m[None, :] >> np.arange(16)[:, None]) & 1
+    return np.where(flips == 1, -1.0, 1.0)
+
+
+def psum_table(rec, off):
+    """The pass's phase sums (layout in csrc/tile.hpp): per combo its
+    records and its lane mask per wave."""
+    ncombo, nrec, rec_off, mask_off = (int(v) for v in rec(off, np.dtype("<u4"), 4))
+    cb = rec(off + 16, np.dtype("<u4"), ncombo + 1).astype(np.int64)
+    recs = rec(off + rec_off, _PREC, nrec)
+    masks = rec(off + mask_off, np.dtype("<u8"), 8 * ncombo).reshape(8, ncombo)
+    assert ncombo % 4 == 0 and cb[0] == 0 and cb[-1] == nrec and np.all(np.diff(cb) >= 0)
+    return cb, recs, masks
+
+
+def epilogue_phase_factors(rec, op, w):
+    """Factors of a phase run applied in a block's epilogue, per (element
+    code, thread code), for tile index w: each combo's sum of the records
+    whose tile-index test holds, added where the thread's bit of its wave's
+    lane mask is set, per group; then subset sums over the element-code
+    bits."""
+    cb, recs, masks = psum_table(rec, int(op["data"]))
+    goff = rec(int(op["tab"]), np.dtype("<u4"), 17).astype(np.int64)
+    assert np.all(np.diff(goff) % 4 == 0)
+    t = np.arange(512, dtype=np.uint64)
     acc = np.zeros((16, 512), np.uint64)
     for g in range(16):
-        for d in terms[off[g]: off[g + 1]]:
-            acc[g] = (acc[g] + np.where(hit(d), np.uint64(int(d["w"])), np.uint64(0))) & np.uint64(0xFFFFFFFF)
+        for c in range(goff[g], goff[g + 1]):
+            s = 0
+            for r in recs[cb[c]: cb[c + 1]]:
+                s += int(r["w"]) if (w & int(r["om"])) == int(r["ov"]) else 0
+            on = (masks[t >> np.uint64(6), c] >> (t & np.uint64(63))) & np.uint64(1)
+            acc[g] = (acc[g] + on * np.uint64(s & 0xFFFFFFFF)) & np.uint64(0xFFFFFFFF)
     for b in range(4):
         for i in range(16):
             if (i >> b) & 1:
@@ -535,9 +560,12 @@ def test_epilogue_runs_reproduce_the_circuit(n, k_max, signs):
             if op["flags"] & 4:
                 # applied in the preceding block's epilogue
                 assert prev is not None and prev[0]["flags"] & 1
-                off = rec(int(op["tab"]), np.dtype("<u4"), 17)
-                terms = rec(int(op["data"]), _ETERM, int(off[-1]))
-                f = epilogue_factors(terms, off, w, bool(op["flags"] & 2))
+                if op["flags"] & 2:
+                    off = rec(int(op["tab"]), np.dtype("<u4"), 17)
+                    f = epilogue_sign_factors(rec(int(op["data"]), _ETERM, int(off[-1])), off, w)
+                else:
+                    assert int(op["data"]) == int(pd["psum"]) and pd["npsum"] > 0
+                    f = epilogue_phase_factors(rec, op, w)
                 n_epi += w == 0
                 n_sign += w == 0 and bool(op["flags"] & 2)
                 epi_map = prev[1]

@@ -40,13 +40,15 @@ def header_functions():
 # Device-image records of the tile kernel (layouts in csrc/tile.hpp).
 _PD = np.dtype([("L", "<i4"), ("c", "<i4"), ("nops", "<i4"), ("remap", "<i4"), ("kmax", "<i4"),
                 ("first_block", "<i4"), ("qmask", "<u8"), ("ops", "<u8"), ("ldoff", "<u8"),
-                ("rmhi", "<u8"), ("rmlo", "<u8"), ("tabs", "<u8"), ("cistab", "<u8")])
+                ("rmhi", "<u8"), ("rmlo", "<u8"), ("tabs", "<u8"), ("cistab", "<u8"), ("psum", "<u8"),
+                ("npsum", "<i4"), ("pad", "<i4")])
 _TOP = np.dtype([("type", "<i4"), ("k", "<i4"), ("lb", "<i4", 6), ("data", "<u8"),
                  ("next_block", "<i4"), ("flags", "<i4"), ("tab", "<u8"), ("next_data", "<u8")])
 _DSUB = np.dtype([("lmask", "<u4"), ("lval", "<u4"), ("neg", "<i4"), ("rows", "<u4"), ("omask", "<u8"),
                   ("oval", "<u8"), ("pr", "<f8"), ("pi", "<f8"), ("turns", "<u8"), ("pad", "<u8")])
 _DTERM = np.dtype([("omask", "<u8"), ("oval", "<u8"), ("turns", "<u8"), ("lmask", "<u4"), ("lval", "<u4")])
 _ETERM = np.dtype([("om", "<u4"), ("ov", "<u4"), ("lm", "<u4"), ("lv", "<u4"), ("w", "<u4"), ("pad", "<u4", 3)])
+_PREC = np.dtype([("om", "<u4"), ("ov", "<u4"), ("w", "<u4"), ("pad", "<u4")])
 
 
 def plan_image(plan):
