@@ -272,8 +272,16 @@ qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits,
  * features are filled in, but no block matrices and no device image (the
  * expensive part), so qvm_run_plan and a block's matrix return QVM_ESTATE.
  * The learned planner scores candidates this way and builds only the chosen
- * one in full.  QVM_EARG for unknown flags. */
+ * one in full.  QVM_PLAN_DEFER_NARROW (tile passes, k_max >= 3): a block of
+ * fewer than 3 qubits costs as much as a 3-qubit block, so when such a
+ * block's gates are the last its pass takes on each of their wires they are
+ * left to a later pass, where they join their successors' block (not in the
+ * last pass, never every block of a pass).  Fewer blocks, sometimes more
+ * passes: a choice for the learned planner (paper, "Quantum circuit
+ * fusion": the fusion scheme is picked by the cost model).  QVM_EARG for
+ * unknown flags. */
 #define QVM_PLAN_NO_IMAGE 1u
+#define QVM_PLAN_DEFER_NARROW 2u
 qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubits,
                               int k_max, int tile_qubits, qvm_dtype dt, uint32_t flags,
                               qvm_plan** out);

@@ -654,7 +654,7 @@ std::vector<R> fragments(const std::vector<cd>& M, int k) {
 
 qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int k_max,
                       int tile_qubits, const uint32_t* partition, qvm_plan** out, bool image,
-                      const int32_t* k_of_pass = nullptr, int n_k_of_pass = 0) {
+                      const int32_t* k_of_pass = nullptr, int n_k_of_pass = 0, bool defer_narrow = false) {
     if (!out) return fail(QVM_EARG, "NULL out");
     *out = nullptr;
     if (n < 1 || n > QVM_MAX_QUBITS) return fail(QVM_EARG, "n_qubits outside 1..34");
@@ -839,6 +839,49 @@ qvm_status build_plan(const qvm_gate* gates, size_t ng, int n, qvm_dtype dt, int
             const int kp = k_of_pass ? k_of_pass[std::min((int)P->passes.size(), n_k_of_pass - 1)] : k_max;
             pp.units = fuse(G, taken, n, kp, T);
             absorb_diagonals(pp.units, G, kp, T);
+            // A block narrower than 3 qubits costs a full 3-qubit block.  When
+            // such a block's gates are the last this pass takes on each of
+            // their wires, they are left to a later pass (which needs those
+            // wires for their successors anyway), where they join the block
+            // of those successors.  Not in the last pass, and never every
+            // block of a pass.
+            if (defer_narrow && left > 0 && kp >= 3) {
+                std::vector<char> defer(pp.units.size(), 0);
+                int nblocks = 0, ndefer = 0;
+                for (size_t ui = 0; ui < pp.units.size(); ++ui) {
+                    const Unit& u = pp.units[ui];
+                    if (!u.block) continue;
+                    ++nblocks;
+                    if (u.qubits.size() >= 3) continue;
+                    std::vector<int> cnt(n, 0);
+                    for (int gi : u.gates)
+                        for (uint64_t m = G[gi].qmask; m; m &= m - 1) ++cnt[__builtin_ctzll(m)];
+                    bool trailing = true;
+                    for (int q = 0; q < n && trailing; ++q)
+                        for (int j = 1; j <= cnt[q] && trailing; ++j) {
+                            const int gj = F.per_q[q][F.ptr[q] - j];
+                            trailing = std::find(u.gates.begin(), u.gates.end(), gj) != u.gates.end();
+                        }
+                    if (trailing) {
+                        defer[ui] = 1;
+                        ++ndefer;
+                    }
+                }
+                if (ndefer && ndefer < nblocks) {
+                    for (size_t ui = 0; ui < pp.units.size(); ++ui) {
+                        if (!defer[ui]) continue;
+                        for (int gi : pp.units[ui].gates) {
+                            for (uint64_t m = G[gi].qmask; m; m &= m - 1) --F.ptr[__builtin_ctzll(m)];
+                            done[gi] = 0;
+                            ++left;
+                            taken.erase(std::find(taken.begin(), taken.end(), gi));
+                        }
+                    }
+                    first = 0;
+                    pp.units = fuse(G, taken, n, kp, T);
+                    absorb_diagonals(pp.units, G, kp, T);
+                }
+            }
         } else {
             // diagonal units ride in the pass of the next block
             while (next_unit < units.size()) {
@@ -1385,9 +1428,9 @@ qvm_status qvm_plan_greedy(const qvm_gate* gates, size_t n_gates, int n_qubits, 
 
 qvm_status qvm_plan_greedy_ex(const qvm_gate* gates, size_t n_gates, int n_qubits, int k_max,
                               int tile_qubits, qvm_dtype dt, uint32_t flags, qvm_plan** out) {
-    if (flags & ~(uint32_t)QVM_PLAN_NO_IMAGE) return fail(QVM_EARG, "unknown plan flags");
+    if (flags & ~(uint32_t)(QVM_PLAN_NO_IMAGE | QVM_PLAN_DEFER_NARROW)) return fail(QVM_EARG, "unknown plan flags");
     return build_plan(gates, n_gates, n_qubits, dt, k_max, tile_qubits, nullptr, out,
-                      (flags & QVM_PLAN_NO_IMAGE) == 0);
+                      (flags & QVM_PLAN_NO_IMAGE) == 0, nullptr, 0, (flags & QVM_PLAN_DEFER_NARROW) != 0);
 }
 
 qvm_status qvm_plan_tile_per_pass(const qvm_gate* gates, size_t n_gates, int n_qubits, int tile_qubits,

@@ -47,6 +47,10 @@ DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
 CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0), ("block", 6, 0),
               ("tile", 3, 13), ("tile", 4, 13), ("tile", 5, 13),
               ("tile", 3, 12), ("tile", 4, 12), ("tile", 5, 12), ("tile", 3, 11)]
+# tile settings whose passes leave narrow trailing blocks to a later pass
+# (QVM_PLAN_DEFER_NARROW): scored beside the others; the model sees their
+# passes as it sees any pass
+DEFER_CANDIDATES = [("tiled", 3, 13), ("tiled", 4, 13), ("tiled", 3, 12)]
 FALLBACK = ("tile", 3, 13)     # the greedy planner's setting when no model is shipped
 CLASSIC = ("block", 5, 0)      # the classic fused-gate simulator: 5-qubit blocks, one pass each
 # tile widths at which the model also picks the block width of every pass
@@ -72,13 +76,14 @@ def cand_for_dtype(c, dtype):
 
 
 def build_plan(ga, n, dtype, cand, image=True, k_of_pass=None):
-    """A candidate plan: (mode, k_max, tile) of the greedy planner, or
+    """A candidate plan: (mode, k_max, tile) of the greedy planner ("tiled":
+    tile passes that leave narrow trailing blocks to a later pass), or
     ("adaptive", k, tile) with the per-pass block widths k_of_pass."""
     mode, k, tile = cand_for_dtype(cand, dtype)
     try:
         if mode == "adaptive":
             return qvm.Plan(ga, n, dtype, tile_qubits=tile, image=image, k_of_pass=k_of_pass)
-        return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile, image=image)
+        return qvm.Plan(ga, n, dtype, k_max=k, tile_qubits=tile, image=image, defer_narrow=mode == "tiled")
     except qvm.QvmError:
         return None        # e.g. a Toffoli does not fit 2-qubit blocks
 
@@ -267,17 +272,20 @@ class LearnedPlanner:
         The candidates are planned for scoring only (no block matrices or
         device image) on host threads (the library's planner is reentrant and
         ctypes releases the GIL), all their passes are scored in one MLP
-        forward, and only the winner is then built in full.  Beside the fixed
-        settings, at each tile width of ADAPTIVE_TILES the model picks every
+        forward, and only the winner is then built in full.  The fixed
+        settings include tile settings that leave narrow trailing blocks to
+        a later pass (DEFER_CANDIDATES).  Beside them, at each tile width of
+        ADAPTIVE_TILES the model picks every
         pass's block width: a tile pass takes the same gates whatever its
         width, so pass i of the fixed-width candidates are alternatives for
         the same work and the pass with the smallest prediction is taken
         (candidate ("adaptive", widest k, tile); the widths are in
         plan.k_of_pass)."""
         from concurrent.futures import ThreadPoolExecutor
-        with ThreadPoolExecutor(max_workers=min(len(CANDIDATES), os.cpu_count() or 1)) as ex:
-            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), CANDIDATES))
-        live = [(c, p) for c, p in zip(CANDIDATES, plans) if p is not None]
+        cands = CANDIDATES + DEFER_CANDIDATES
+        with ThreadPoolExecutor(max_workers=min(len(cands), os.cpu_count() or 1)) as ex:
+            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), cands))
+        live = [(c, p) for c, p in zip(cands, plans) if p is not None]
         feats = [plan_features(p) for _, p in live]
         rows = np.concatenate(feats)
         if len(rows) == 0:                   # nothing to run: every plan is empty
@@ -507,7 +515,7 @@ def explain(planner, n, gates, x=0, dtype="c64", measure=True):
     cand, chosen, pred = planner.choose(ga, n, dtype)
     rows = []
     sv = qvm.StateVector(n, dtype, init=0) if measure else None
-    for c in CANDIDATES:
+    for c in CANDIDATES + DEFER_CANDIDATES:
         p = build_plan(ga, n, dtype, c)
         if p is None:
             continue

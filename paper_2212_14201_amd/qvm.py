@@ -439,6 +439,7 @@ def _declare_plan(L):
 
 
 QVM_PLAN_NO_IMAGE = 1
+QVM_PLAN_DEFER_NARROW = 2
 
 
 class Plan:
@@ -447,10 +448,12 @@ class Plan:
     image=False builds it for scoring only (schedule, statistics and pass
     features without block matrices or device image); such a plan cannot run.
     k_of_pass: tile passes whose block width is chosen per pass
-    (qvm_plan_tile_per_pass; k_max is then ignored)."""
+    (qvm_plan_tile_per_pass; k_max is then ignored).  defer_narrow: tile
+    passes leave blocks narrower than 3 qubits that end their wires' work in
+    the pass to a later pass (QVM_PLAN_DEFER_NARROW)."""
 
     def __init__(self, gates, n: int, dtype: str = "c64", k_max: int = 5, tile_qubits: int = 0,
-                 partition=None, image: bool = True, k_of_pass=None):
+                 partition=None, image: bool = True, k_of_pass=None, defer_narrow: bool = False):
         _declare_plan(lib())
         self.gates = gates if isinstance(gates, GateArray) else GateArray(gates)
         self.n = int(n)
@@ -458,6 +461,9 @@ class Plan:
         self.k_max, self.tile_qubits, self.image = int(k_max), int(tile_qubits), bool(image)
         h = _vp()
         self.k_of_pass = None if k_of_pass is None else [int(k) for k in k_of_pass]
+        self.defer_narrow = bool(defer_narrow)
+        if defer_narrow and (k_of_pass is not None or partition is not None):
+            raise ValueError("defer_narrow applies to the greedy planner only")
         if k_of_pass is not None:
             if partition is not None:
                 raise ValueError("k_of_pass and partition are exclusive")
@@ -468,7 +474,7 @@ class Plan:
                                                ks.ctypes.data_as(_i32p), int(ks.size), _dt(dtype), flags,
                                                ctypes.byref(h)))
         elif partition is None:
-            flags = 0 if image else QVM_PLAN_NO_IMAGE
+            flags = (0 if image else QVM_PLAN_NO_IMAGE) | (QVM_PLAN_DEFER_NARROW if defer_narrow else 0)
             check(lib().qvm_plan_greedy_ex(self.gates.ptr(), self.gates.n, self.n, int(k_max),
                                            int(tile_qubits), _dt(dtype), flags, ctypes.byref(h)))
         elif not image:

@@ -258,3 +258,28 @@ def test_fused_epilogue_sign_runs(n, k_max):
     print(f"n={n} k={k_max} {plan.stats()} epilogue sign runs {ns} err={err:.2e} tol={tol:.2e}")
     assert ns >= 5
     assert err <= tol
+
+
+@pytest.mark.parametrize("case,n,k_max,tile,dtype", [
+    ("qftbrick", 16, 3, 11, "c64"), ("qftbrick", 16, 3, 11, "c128"), ("qftbrick", 20, 3, 13, "c64"),
+    ("qftbrick", 22, 4, 13, "c64"), ("mixed", 14, 3, 10, "c64"), ("mixed", 14, 4, 10, "c128")])
+def test_fused_defer_narrow(case, n, k_max, tile, dtype):
+    """Plans whose tile passes leave narrow trailing blocks to a later pass
+    (the learned planner's "tiled" candidates) against the oracle; each case
+    is one where the deferral changes the plan."""
+    if case == "qftbrick":
+        init, gates = qft_then_brick(n, 12, 600 + n)
+    else:
+        init, gates = (29 * n) % (1 << n), random_mixed_circuit(n, 200, 700 + n, kmax=3, max_ctrl=0)
+    plan = qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile, defer_narrow=True)
+    base = qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile, image=False).stats()
+    st = plan.stats()
+    assert (st["blocks"], st["passes"], st["blocks_by_k"]) != (base["blocks"], base["passes"], base["blocks_by_k"])
+    sv = qvm.StateVector(n, dtype, init=init)
+    plan.run(sv)
+    want = oracle.simulate(n, gates, init=init)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = C128_TOL if dtype == "c128" else plan_bound(plan)
+    print(f"{case} n={n} k={k_max} tile={tile} {dtype} {st} (without: {base['passes']} passes, "
+          f"{base['blocks']} blocks) err={err:.2e} tol={tol:.2e}")
+    assert err <= tol

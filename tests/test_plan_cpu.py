@@ -10,7 +10,7 @@ import pytest
 import oracle
 from tests.util import (_DSUB, _DTERM, _ETERM, _PREC, _TOP, blocks_and_diagonals, plan_image,
                         tile_blocks_outer_diagonals)
-from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit,
+from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit, qft_then_brick,
                        random_mixed_circuit, random_planner_circuit)
 
 qvm = pytest.importorskip("paper_2212_14201_amd.qvm")
@@ -40,8 +40,8 @@ def on_wires(gates):
     return out
 
 
-def check_plan(gates, n, k_max, tile, dtype="c64", relabeled_swaps=None):
-    plan = qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile)
+def check_plan(gates, n, k_max, tile, dtype="c64", relabeled_swaps=None, defer_narrow=False):
+    plan = qvm.Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile, defer_narrow=defer_narrow)
     st = plan.stats()
     units = units_in_order(plan, len(gates))
     wg = on_wires(gates)
@@ -67,6 +67,36 @@ def test_random_circuits_plans_valid(k_max, tile):
         pytest.skip("tile narrower than a block")
     gates = random_mixed_circuit(n, 120, 100 + k_max, kmax=min(3, k_max), max_ctrl=max(0, k_max - 3))
     check_plan(gates, n, k_max, tile)
+
+
+@pytest.mark.parametrize("n,k_max,tile", [(10, 3, 8), (10, 4, 8), (12, 3, 9), (14, 3, 10), (14, 4, 10)])
+def test_defer_narrow_plans_valid(n, k_max, tile):
+    """Tile passes that leave narrow trailing blocks to a later pass: the
+    plans stay valid (per-wire order, block matrices) on random circuits
+    and on the QFT followed by a brick."""
+    gates = random_mixed_circuit(n, 200, 700 + n + k_max, kmax=3, max_ctrl=max(0, k_max - 3))
+    check_plan(gates, n, k_max, tile, defer_narrow=True)
+    _, gates = qft_then_brick(n, 12, 600 + n)
+    check_plan(gates, n, k_max, tile, defer_narrow=True)
+    with pytest.raises(ValueError):
+        qvm.Plan(gates, n, "c64", tile_qubits=tile, k_of_pass=[3], defer_narrow=True)
+
+
+def test_defer_narrow_on_the_30_qubit_workload():
+    """On the 30-qubit workload (QFT + 30 brick layers, 3-qubit blocks in
+    13-qubit tiles) every narrow block but those of the last pass is left
+    to a later pass, where it joins a 3-qubit block: 229 -> 220 blocks and
+    18 -> 17 passes."""
+    cfg = config_circuit("qft30")
+    base = qvm.Plan(cfg["gates"], 30, "c64", k_max=3, tile_qubits=13, image=False)
+    plan = qvm.Plan(cfg["gates"], 30, "c64", k_max=3, tile_qubits=13, defer_narrow=True)
+    sb, sd = base.stats(), plan.stats()
+    assert sb["blocks_by_k"][1] + sb["blocks_by_k"][2] > 0
+    last = sd["passes"] - 1
+    for b in range(sd["blocks"]):
+        blk = plan.block(b)
+        assert blk["k_true"] == 3 or blk["pass"] == last
+    assert sd["blocks"] < sb["blocks"] and sd["passes"] <= sb["passes"]
 
 
 def test_layered_and_qft_plans():
@@ -189,7 +219,11 @@ def test_plan_flags_rejected():
     L = qvm.lib()
     ga = qvm.GateArray([Gate("h", (0,))])
     h = qvm.ctypes.c_void_p()
-    st = L.qvm_plan_greedy_ex(ga.ptr(), ga.n, 3, 3, 0, qvm.QVM_C64, 2, qvm.ctypes.byref(h))
+    st = L.qvm_plan_greedy_ex(ga.ptr(), ga.n, 3, 3, 0, qvm.QVM_C64, 4, qvm.ctypes.byref(h))
+    assert qvm.STATUS[st] == "QVM_EARG" and not h.value
+    ks = np.array([3], np.int32)
+    st = L.qvm_plan_tile_per_pass(ga.ptr(), ga.n, 3, 3, ks.ctypes.data_as(qvm._i32p), 1, qvm.QVM_C64,
+                                  qvm.QVM_PLAN_DEFER_NARROW, qvm.ctypes.byref(h))
     assert qvm.STATUS[st] == "QVM_EARG" and not h.value
 
 
