@@ -406,7 +406,7 @@ def max_abs_vs_c128(fused, plain, chunk=1 << 26):
 
 # fixed settings timed beside the learned choice on held-out circuits: every
 # tile setting (the fallback among them) and the classic one block per pass
-EVAL_CANDIDATES = [c for c in CANDIDATES if c[0] == "tile"] + [CLASSIC]
+EVAL_CANDIDATES = [c for c in CANDIDATES if c[0] == "tile"] + DEFER_CANDIDATES + [CLASSIC]
 
 
 def evaluate(planner, first, count, dtype="c64", reps=2, check=True, n_range=(26, 32),

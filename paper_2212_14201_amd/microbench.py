@@ -5,7 +5,7 @@ of a single kernel class, and with ``--kernel copy`` to read the same
 counters for a plain device copy of known size (the scale factor).
 
     python -m paper_2212_14201_amd.microbench --kernel dense1 --n 30 --dtype c128
-    python -m paper_2212_14201_amd.microbench --kernel tile --n 30 --dtype c64
+    python -m paper_2212_14201_amd.microbench --kernel tile --n 30 --dtype c64 --defer
     python -m paper_2212_14201_amd.microbench --kernel copy --n 30 --dtype c128
     python -m paper_2212_14201_amd.microbench --kernel stream --n 30 --launches 5
     python -m paper_2212_14201_amd.microbench --kernel blocks --k 4 --blocks 32 --n 30 --launches 2
@@ -29,6 +29,9 @@ def main():
     ap.add_argument("--tile", type=int, default=13, help="blocks: tile qubits of the pass")
     ap.add_argument("--classic", action="store_true",
                     help="tile: the classic plan (one 5-qubit block per pass) instead of 3-qubit blocks in tiles")
+    ap.add_argument("--defer", action="store_true",
+                    help="tile: passes leave narrow trailing blocks to a later pass (the learned planner's "
+                         "choice for the 30-qubit workload)")
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--launches", type=int, default=3)
@@ -132,7 +135,8 @@ def main():
         cfg = config_circuit("qft30") if a.n == 30 else None
         gates = cfg["gates"] if cfg else [Gate("h", (q,)) for q in range(a.n)]
         plan = (qvm.Plan(gates, a.n, a.dtype, k_max=5, tile_qubits=0) if a.classic
-                else qvm.Plan(gates, a.n, a.dtype, k_max=3, tile_qubits=13 if a.dtype == "c64" else 12))
+                else qvm.Plan(gates, a.n, a.dtype, k_max=3, tile_qubits=13 if a.dtype == "c64" else 12,
+                              defer_narrow=a.defer))
         for _ in range(a.launches):
             sv.init_basis(0)
             plan.run(sv)
