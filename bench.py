@@ -431,7 +431,7 @@ def main():
         if planner is not None:
             r["choice"], plan, r["predicted_ms"] = planner.choose(ga, n, "c64")
         else:
-            plan = qvm.Plan(ga, n, "c64", k_max=args.k_max, tile_qubits=args.tile)
+            plan = qvm.Plan(ga, n, "c64", k_max=args.k_max, tile_qubits=args.tile, defer_narrow=args.tile > 0)
         t1 = time.perf_counter()
         fused.init_basis(x)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -564,9 +564,9 @@ def main():
                           "TFLOPs": v["flops"] / (v["total_ms"] / 1e3) / 1e12 if v["total_ms"] else None}
                       for k, v in kstats.items()}
     # outside the timed steps: the greedy planner without the model, at the
-    # setting it falls back to (3-qubit blocks in 13-qubit tiles) and at the
-    # classic fused-gate setting (one 5-qubit block per pass), beside the
-    # learned choice
+    # setting it falls back to (3-qubit blocks in 13-qubit tiles, narrow
+    # trailing blocks deferred) and at the classic fused-gate setting (one
+    # 5-qubit block per pass), beside the learned choice
     if planner is not None:
         from paper_2212_14201_amd import learned_planner
         base = {}

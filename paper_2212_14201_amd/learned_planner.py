@@ -51,7 +51,10 @@ CANDIDATES = [("block", 2, 0), ("block", 3, 0), ("block", 4, 0), ("block", 5, 0)
 # (QVM_PLAN_DEFER_NARROW): scored beside the others; the model sees their
 # passes as it sees any pass
 DEFER_CANDIDATES = [("tiled", 3, 13), ("tiled", 4, 13), ("tiled", 3, 12)]
-FALLBACK = ("tile", 3, 13)     # the greedy planner's setting when no model is shipped
+# the setting used without a model: 3-qubit blocks in 13-qubit tiles with
+# narrow trailing blocks deferred (the fastest fixed setting on held-out
+# random and mixture circuits and on the 30-qubit workload)
+FALLBACK = ("tiled", 3, 13)
 CLASSIC = ("block", 5, 0)      # the classic fused-gate simulator: 5-qubit blocks, one pass each
 # tile widths at which the model also picks the block width of every pass
 ADAPTIVE_TILES = (13, 12)

@@ -182,11 +182,13 @@ class Circuit:
 
 
 def plan(circuit, n: int | None = None, dtype: str = "c64", planner: str = "greedy",
-         k_max: int = 3, tile_qubits: int = 13) -> "Plan":
+         k_max: int = 3, tile_qubits: int = 13, defer_narrow: bool = True) -> "Plan":
     """A fused plan for a Circuit (or gate list).  planner="greedy": the
-    greedy planner at (k_max, tile_qubits); planner="learned": the shipped
-    cost model's choice among the candidate settings (needs the GPU for the
-    model and fails when no model is shipped)."""
+    greedy planner at (k_max, tile_qubits), by default with narrow trailing
+    blocks left to a later pass (defer_narrow, tile passes only);
+    planner="learned": the shipped cost model's choice among the candidate
+    settings (needs the GPU for the model and fails when no model is
+    shipped)."""
     if isinstance(circuit, Circuit):
         n = circuit.n if n is None else n
         gates = circuit.gates
@@ -195,7 +197,8 @@ def plan(circuit, n: int | None = None, dtype: str = "c64", planner: str = "gree
     if n is None:
         raise ValueError("n is required for a plain gate list")
     if planner == "greedy":
-        return Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile_qubits)
+        return Plan(gates, n, dtype, k_max=k_max, tile_qubits=tile_qubits,
+                    defer_narrow=defer_narrow and tile_qubits > 0)
     if planner == "learned":
         from .learned_planner import load_default
         lp = load_default()
