@@ -55,6 +55,11 @@ DEFER_CANDIDATES = [("tiled", 3, 13), ("tiled", 4, 13), ("tiled", 3, 12)]
 # narrow trailing blocks deferred (the fastest fixed setting on held-out
 # random and mixture circuits and on the 30-qubit workload)
 FALLBACK = ("tiled", 3, 13)
+# the settings the planner scores: 2-qubit blocks one per pass are left out
+# (every pass streams the whole state for a 2-qubit block; on the 30-qubit
+# workload 436 passes, 8.4x the fallback's time, and the slowest candidate
+# to plan); the fallback is planned in full while the others are scored
+SCORED = [c for c in CANDIDATES if c != ("block", 2, 0)] + DEFER_CANDIDATES
 CLASSIC = ("block", 5, 0)      # the classic fused-gate simulator: 5-qubit blocks, one pass each
 # tile widths at which the model also picks the block width of every pass
 ADAPTIVE_TILES = (13, 12)
@@ -275,9 +280,10 @@ class LearnedPlanner:
         The candidates are planned for scoring only (no block matrices or
         device image) on host threads (the library's planner is reentrant and
         ctypes releases the GIL), all their passes are scored in one MLP
-        forward, and only the winner is then built in full.  The fixed
-        settings include tile settings that leave narrow trailing blocks to
-        a later pass (DEFER_CANDIDATES).  Beside them, at each tile width of
+        forward, and only the winner is then built in full (the fallback
+        setting is built in full while the others are scored, as it often
+        wins).  The fixed settings (SCORED) include tile settings that leave
+        narrow trailing blocks to a later pass (DEFER_CANDIDATES).  Beside them, at each tile width of
         ADAPTIVE_TILES the model picks every
         pass's block width: a tile pass takes the same gates whatever its
         width, so pass i of the fixed-width candidates are alternatives for
@@ -285,9 +291,9 @@ class LearnedPlanner:
         (candidate ("adaptive", widest k, tile); the widths are in
         plan.k_of_pass)."""
         from concurrent.futures import ThreadPoolExecutor
-        cands = CANDIDATES + DEFER_CANDIDATES
+        cands = SCORED
         with ThreadPoolExecutor(max_workers=min(len(cands), os.cpu_count() or 1)) as ex:
-            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=False), cands))
+            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=c == FALLBACK), cands))
         live = [(c, p) for c, p in zip(cands, plans) if p is not None]
         feats = [plan_features(p) for _, p in live]
         rows = np.concatenate(feats)
@@ -312,6 +318,10 @@ class LearnedPlanner:
         # model's error: an adaptive plan must beat the fixed settings by a
         # margin to be taken
         pred, cand, ks = min(options, key=lambda t: t[0] * (1.0 + self.adaptive_margin if t[2] else 1.0))
+        if cand == FALLBACK and ks is None:
+            plan = dict(live)[cand]          # built in full while the others were scored
+            plan.k_of_pass = None
+            return cand, plan, pred
         plan = build_plan(ga, n, dtype, cand, k_of_pass=ks)
         plan.k_of_pass = ks
         return cand, plan, pred
