@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import C128_TOL, U32, blocks_and_diagonals, epilogue_runs
+from tests.util import C128_TOL, U32, blocks_and_diagonals, epilogue_runs, long_phase_run
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit, qft_then_brick,
                        random_mixed_circuit, random_planner_circuit, random_pauli_sum)
 
@@ -282,4 +282,22 @@ def test_fused_defer_narrow(case, n, k_max, tile, dtype):
     tol = C128_TOL if dtype == "c128" else plan_bound(plan)
     print(f"{case} n={n} k={k_max} tile={tile} {dtype} {st} (without: {base['passes']} passes, "
           f"{base['blocks']} blocks) err={err:.2e} tol={tol:.2e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("count", [200, 1100])
+def test_fused_long_phase_run_after_a_block(count):
+    """complex64, 13 qubits: a run of controlled phases after a block, in the
+    block's epilogue through the pass's phase sums (200 gates) or on its own
+    once its bound passes the phase-sum area (1,100 gates), against the
+    oracle."""
+    n = 13
+    gates = long_phase_run(n, count, 5100 + count)
+    init = 77
+    sv, plan = run_fused(n, gates, "c64", 3, 13, init)
+    want = oracle.simulate(n, gates, init=init)
+    err = float(np.max(np.abs(sv.amplitudes() - want)))
+    tol = plan_bound(plan)
+    print(f"{count} phases: {plan.stats()} epilogue runs {epilogue_runs(plan)} err={err:.2e} tol={tol:.2e}")
+    assert (epilogue_runs(plan) > 0) == (count < 1024)
     assert err <= tol

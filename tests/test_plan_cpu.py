@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.util import (_DSUB, _DTERM, _ETERM, _PREC, _TOP, blocks_and_diagonals, plan_image,
+from tests.util import (_DSUB, _DTERM, _ETERM, _PREC, _TOP, blocks_and_diagonals, long_phase_run, plan_image,
                         tile_blocks_outer_diagonals)
 from workloads import (Gate, config_circuit, layered_u3_cz, qft_circuit, qft_then_brick,
                        random_mixed_circuit, random_planner_circuit)
@@ -97,6 +97,24 @@ def test_defer_narrow_on_the_30_qubit_workload():
         blk = plan.block(b)
         assert blk["k_true"] == 3 or blk["pass"] == last
     assert sd["blocks"] < sb["blocks"] and sd["passes"] <= sb["passes"]
+
+
+@pytest.mark.parametrize("count,epilogue", [(200, True), (1100, False)])
+def test_phase_sums_bounded(count, epilogue):
+    """A phase run rides in the block epilogue only while the pass's phase
+    sums stay within their LDS area (kPSumMax = 1024 combos, bounded before
+    the layout is fixed); a longer run is applied on its own.  Both plans are
+    valid (oracle validator, block matrices; tests/test_gpu_fused.py runs
+    them against the oracle's state)."""
+    n = 13
+    gates = long_phase_run(n, count, 5100 + count)
+    plan, _ = check_plan(gates, n, 3, 13)
+    rec, passes = plan_image(plan)
+    assert len(passes) == 1 and 0 <= int(passes[0]["npsum"]) <= 1024
+    ops = rec(int(passes[0]["ops"]), _TOP, int(passes[0]["nops"]))
+    runs = [op for op in ops if op["type"] == 2]
+    assert runs and any(op["flags"] & 4 for op in runs) == epilogue
+    assert (int(passes[0]["psum"]) != 0) == epilogue
 
 
 def test_layered_and_qft_plans():

@@ -142,3 +142,17 @@ def cdf_eps(tau):
     most tau: sum_i |dp_i| <= 2 tau + tau^2 bounds the error of every
     cumulative probability, counted once for C(s) and once for the total."""
     return 2.0 * (2.0 * tau + tau * tau)
+
+
+
+def long_phase_run(n, count, seed):
+    """Three U3 gates (one block), then `count` controlled phases with
+    distinct angles on random qubit pairs: a diagonal run of `count` terms
+    after a block."""
+    from workloads import Gate
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gates = [Gate("u3", (q,), (), tuple(rng.uniform(0, 2 * np.pi, 3))) for q in range(3)]
+    for _ in range(count):
+        t, c = (int(v) for v in rng.choice(n, 2, replace=False))
+        gates.append(Gate("p", (t,), (c,), (float(rng.uniform(0, 2 * np.pi)),)))
+    return gates
