@@ -86,6 +86,31 @@ __global__ __launch_bounds__(kTPB) void k_dense(typename C2<R>::T* __restrict__ 
     }
 }
 
+// A one-qubit complex128 gate with one amplitude (one 16-byte piece) per
+// lane, the streaming shape above: lanes 0-31 of a wave load the first
+// amplitude of 32 consecutive pairs, lanes 32-63 the second; partners trade
+// their values across the wave's halves (lane ^ 32) and each lane writes its
+// own row of the 2 x 2 product.  The loop runs per wave, so every lane of a
+// wave takes part in the exchange; lanes past the end store nothing.
+__global__ __launch_bounds__(kTPB) void k_dense1_lanes(double2* __restrict__ psi, DenseArgs<double, 1> a) {
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const uint64_t waves = (a.items + 31) / 32;
+    const uint64_t wstride = (uint64_t)gridDim.x * (kTPB / 64);
+    const double r0 = a.m[4 * h], i0 = a.m[4 * h + 1], r1 = a.m[4 * h + 2], i1 = a.m[4 * h + 3];
+    for (uint64_t wv = (uint64_t)blockIdx.x * (kTPB / 64) + (threadIdx.x >> 6); wv < waves; wv += wstride) {
+        const uint64_t w = wv * 32 + (lane & 31);
+        const bool act = w < a.items;
+        const uint64_t idx = (deposit(act ? w : 0, a.fixed) | a.cmask) + a.off[h];
+        const double2 v = act ? ld_stream(psi + idx) : make_double2(0.0, 0.0);
+        const double2 u = make_double2(__shfl_xor(v.x, 32, 64), __shfl_xor(v.y, 32, 64));
+        const double2 v0 = h ? u : v, v1 = h ? v : u;
+        double2 o;
+        o.x = r0 * v0.x - i0 * v0.y + r1 * v1.x - i1 * v1.y;
+        o.y = r0 * v0.y + i0 * v0.x + r1 * v1.y + i1 * v1.x;
+        if (act) st_stream(psi + idx, o);
+    }
+}
+
 template <typename R> struct DiagArgs {
     uint64_t items, cmask;
     int k;
@@ -236,8 +261,12 @@ static qvm_status launch_dense_k(qvm_sv* sv, const LOp& op) {
     }
     const double touched = (double)a.items * (1 << K);
     const int tok = prof_begin(sv);
-    hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(kTPB), 0, sv->stream,
-                       (T*)sv->amps, a);
+    if constexpr (K == 1 && sizeof(R) == 8)
+        hipLaunchKernelGGL(k_dense1_lanes, dim3(grid_for(2 * a.items)), dim3(kTPB), 0, sv->stream,
+                           (T*)sv->amps, a);
+    else
+        hipLaunchKernelGGL((k_dense<R, K>), dim3(grid_for(a.items)), dim3(kTPB), 0, sv->stream,
+                           (T*)sv->amps, a);
     QVM_LAUNCH_CHECK(sv);
     prof_end(sv, tok, PK_DENSE1 + K - 1, 2.0 * touched * sizeof(T), touched * 8.0 * (1 << K));
     return QVM_OK;
