@@ -76,6 +76,18 @@ def _declare():
     return L
 
 
+_POOL = None
+
+
+def _pool():
+    """The host threads that plan the candidates (kept between calls)."""
+    global _POOL
+    if _POOL is None:
+        from concurrent.futures import ThreadPoolExecutor
+        _POOL = ThreadPoolExecutor(max_workers=min(len(SCORED), os.cpu_count() or 1))
+    return _POOL
+
+
 def cand_for_dtype(c, dtype):
     mode, k, tile = c
     if dtype == "c128" and tile > 12:
@@ -290,12 +302,12 @@ class LearnedPlanner:
         the same work and the pass with the smallest prediction is taken
         (candidate ("adaptive", widest k, tile); the widths are in
         plan.k_of_pass)."""
-        from concurrent.futures import ThreadPoolExecutor
-        cands = SCORED
-        with ThreadPoolExecutor(max_workers=min(len(cands), os.cpu_count() or 1)) as ex:
-            plans = list(ex.map(lambda c: build_plan(ga, n, dtype, c, image=c == FALLBACK), cands))
-        live = [(c, p) for c, p in zip(cands, plans) if p is not None]
-        feats = [plan_features(p) for _, p in live]
+        def scored(c):
+            p = build_plan(ga, n, dtype, c, image=c == FALLBACK)
+            return (c, p, plan_features(p)) if p is not None else None
+        done = [r for r in _pool().map(scored, SCORED) if r is not None]
+        live = [(c, p) for c, p, _ in done]
+        feats = [f for _, _, f in done]
         rows = np.concatenate(feats)
         if len(rows) == 0:                   # nothing to run: every plan is empty
             c0 = live[0][0]
