@@ -215,6 +215,26 @@ __global__ __launch_bounds__(kTPB) void k_swappair(typename C2<R>::T* __restrict
     }
 }
 
+// The complex128 form with one amplitude per lane: lanes 0-31 of a wave
+// take 32 consecutive pairs' first amplitudes, lanes 32-63 their partners,
+// and each lane stores its amplitude at its partner's index.  The wave's
+// load completes for every lane before its store is issued (the store
+// waits for the loaded value), so no lane overwrites an amplitude another
+// lane has still to read; different waves touch different pairs.
+__global__ __launch_bounds__(kTPB) void k_swappair_lanes(double2* __restrict__ psi, uint64_t items,
+                                                         uint64_t fixed, uint64_t cval, uint64_t xmask) {
+    const int lane = threadIdx.x & 63, h = lane >> 5;
+    const uint64_t waves = (items + 31) / 32;
+    const uint64_t wstride = (uint64_t)gridDim.x * (kTPB / 64);
+    for (uint64_t wv = (uint64_t)blockIdx.x * (kTPB / 64) + (threadIdx.x >> 6); wv < waves; wv += wstride) {
+        const uint64_t w = wv * 32 + (lane & 31);
+        if (w >= items) continue;
+        const uint64_t idx = deposit(w, fixed) | cval;
+        const uint64_t mine = h ? idx ^ xmask : idx;
+        st_stream(psi + (mine ^ xmask), ld_stream(psi + mine));
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_basis(typename C2<R>::T* __restrict__ psi, uint64_t N,
                                                uint64_t idx) {
@@ -323,8 +343,12 @@ static qvm_status launch_op_t(qvm_sv* sv, const LOp& op) {
             uint64_t fixed = op.cond_mask | op.hbit;
             uint64_t items = 1ull << (sv->n - popc(fixed));
             const int tok = prof_begin(sv);
-            hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(kTPB), 0, sv->stream,
-                               (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
+            if constexpr (sizeof(R) == 8)
+                hipLaunchKernelGGL(k_swappair_lanes, dim3(grid_for(2 * items)), dim3(kTPB), 0, sv->stream,
+                                   (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
+            else
+                hipLaunchKernelGGL((k_swappair<R>), dim3(grid_for(items)), dim3(kTPB), 0, sv->stream,
+                                   (T*)sv->amps, items, fixed, op.cond_val, op.xmask);
             QVM_LAUNCH_CHECK(sv);
             prof_end(sv, tok, PK_SWAP, 4.0 * items * sizeof(T), 0.0);
             return QVM_OK;

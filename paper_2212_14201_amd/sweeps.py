@@ -9,8 +9,8 @@ context curves, not targets):
   circuit  the paper's random circuit, a rotation layer (RX, RY, RZ on every
            qubit) and a CNOT layer (target i, control (i+1) mod n) repeated,
            over qubit counts: plain complex128 against the fused complex64
-           path with the shipped learned planner (greedy with 4-qubit blocks
-           in 13-qubit tiles if no model is present), planning included.
+           path with the shipped learned planner (the greedy planner at its
+           fallback setting if no model is present), planning included.
 
     python -m paper_2212_14201_amd.sweeps gates --n 16 20 24 28 30
     python -m paper_2212_14201_amd.sweeps circuit --n 16 20 24 28 30 --layers 10
@@ -125,8 +125,8 @@ def sweep_circuit(ns, layers=10, seed=11):
                 cand, plan, _ = planner.choose(ga, n, "c64")
                 rec["planner"] = "learned: %s, k_max %d, tile %d" % cand
             else:
-                plan = qvm.Plan(ga, n, "c64", k_max=3, tile_qubits=13)
-                rec["planner"] = "greedy: k_max 3, tile 13"
+                plan = learned_planner.build_plan(ga, n, "c64", learned_planner.FALLBACK)
+                rec["planner"] = "greedy: %s, k_max %d, tile %d" % learned_planner.FALLBACK
             t1 = time.perf_counter()
             plan.run(fused)
             torch.cuda.synchronize()
